@@ -1,0 +1,178 @@
+"""Row-by-row formation of the WQ mass and stiffness matrices, for the oracle
+(test infrastructure only).
+
+Conventions (0-based): the row index is the test function i, the column the
+trial function j (the weights belong to the test function, Section 2); the
+linear index of (i1, i2, i3) is i1 + n1 (i2 + n2 i3) (Section 3, direction 1
+fastest); columns of a row are in increasing linear order.  No symmetrisation
+and no boundary conditions.
+
+* ``Problem.row(..., method="direct")`` -- the plain nested WQ sum of
+  eq. (6.2) (label eq:massquadrature): for every j in I_i, the sum over
+  q in Q_i of the product over directions of w_{k,i_k,q_k} B_{j_k}(x_{q_k})
+  times the coefficient at x_q, written as one unfactorized sum.  For the
+  stiffness, the analogue from eq. (3.3) (label eq:stiff): the sum over the
+  d^2 pairs (l, m) (l = derivative direction of the test function, m = of the
+  trial function) where direction k uses the rule w^(alpha_k, beta_k) with
+  alpha_k = [k == m] (trial) and beta_k = [k == l] (test), the trial factor
+  B^(alpha_k)_{j_k}, and the coefficient c_lm.
+* ``Problem.row(..., method="sumfact")`` -- Algorithm 3 (eq. 6.3, label
+  eq:sumfactorization): C_i x_3 (B W)_3 x_2 (B W)_2 x_1 (B W)_1 as successive
+  mode products; the stiffness is the sum of the d^2 such products.
+* ``Problem.sgq_matrices`` -- element-wise standard Gauss quadrature (SGQ,
+  Section 1) with p+1 Gauss-Legendre points per direction and element; exact
+  for affine maps and constant coefficients, used by the exactness pins.
+
+Pins (tests/test_oracle_assembly.py): direct == sum-factorized (the identity
+between eq:massquadrature and eq:sumfactorization), affine exactness against
+a closed Kronecker formula of exact 1D integrals and against SGQ, S 1 = 0,
+mass row sums, total mass = volume, the nnz formula of Section 3.
+"""
+from __future__ import annotations
+
+from typing import Callable, Optional, Sequence
+
+import numpy as np
+
+from .geometry import coefficients_from_jacobian, map_and_jacobian
+from .rules import rules_for
+
+
+def mode_product(X: np.ndarray, A: np.ndarray, m: int) -> np.ndarray:
+    """(X x_m A)[..., k_m, ...] = sum_j A[k_m, j] X[..., j, ...]  (Section 6)."""
+    return np.moveaxis(np.tensordot(A, X, axes=(1, m)), 0, m)
+
+
+class Problem:
+    """One 3D single-patch problem: knots, degree, control net, coefficient."""
+
+    def __init__(self, knots3: Sequence, p: int, ctrl: np.ndarray,
+                 coef: Optional[Callable[[np.ndarray], np.ndarray]] = None):
+        if len(knots3) != 3:
+            raise ValueError("3D problems only")
+        self.p = p
+        self.knots3 = [np.asarray(k, dtype=np.float64) for k in knots3]
+        self.rules = [rules_for(list(k), p) for k in self.knots3]
+        self.n = tuple(r.n for r in self.rules)
+        self.ctrl = np.asarray(ctrl, dtype=np.float64)
+        if self.ctrl.shape != (self.n[2], self.n[1], self.n[0], 3):
+            raise ValueError("control net shape must be (n3, n2, n1, 3)")
+        self.coef = coef
+        self.B = [(r.table64(0), r.table64(1)) for r in self.rules]
+
+    # ---- indices ---------------------------------------------------------
+    def multi(self, row: int):
+        n1, n2, _ = self.n
+        return row % n1, (row // n1) % n2, row // (n1 * n2)
+
+    def row_columns(self, row: int) -> np.ndarray:
+        i = self.multi(row)
+        I = [self.rules[k].I[i[k]] for k in range(3)]
+        n1, n2, _ = self.n
+        return np.array([j1 + n1 * (j2 + n2 * j3) for j3 in I[2] for j2 in I[1] for j1 in I[0]],
+                        dtype=np.int64)
+
+    def csr_pattern(self):
+        N = self.n[0] * self.n[1] * self.n[2]
+        cols = [self.row_columns(r) for r in range(N)]
+        row_ptr = np.zeros(N + 1, dtype=np.int64)
+        row_ptr[1:] = np.cumsum([len(c) for c in cols])
+        return row_ptr, np.concatenate(cols).astype(np.int32)
+
+    # ---- per-row data ----------------------------------------------------
+    def operator(self, k: int, ik: int, alpha: int, beta: int) -> np.ndarray:
+        """B^(k,ik) W^(k,ik) of Section 6 for pairing (alpha, beta):
+        T[j, q] = B^(alpha)_j(x_q) w^(alpha,beta)_{ik,q}, j in I_ik, q in Q_ik."""
+        r = self.rules[k]
+        Bt = self.B[k][alpha][np.ix_(r.I[ik], r.Q[ik])]
+        return Bt * r.w64[(alpha, beta)][ik][None, :]
+
+    def row_fields(self, row: int):
+        """Coefficients on the block Q_i1 x Q_i2 x Q_i3 (arrays indexed
+        [q1, q2, q3]): mass factor det J, stiffness K (3x3), and F."""
+        i = self.multi(row)
+        X = [self.rules[k].x64[self.rules[k].Q[i[k]]] for k in range(3)]
+        F, J = map_and_jacobian(self.knots3, self.p, self.ctrl, X[0], X[1], X[2])
+        a = None if self.coef is None else self.coef(F.reshape(-1, 3)).reshape(F.shape[:3])
+        det, K = coefficients_from_jacobian(J, a)
+        return det, K, F
+
+    # ---- formation ---------------------------------------------------------
+    def row(self, row: int, which: str, method: str = "sumfact") -> np.ndarray:
+        """Values of the row in increasing column order."""
+        i = self.multi(row)
+        det, K, _ = self.row_fields(row)
+        if which == "mass":
+            terms = [((0, 0, 0), (0, 0, 0), det)]
+        elif which == "stiff":
+            terms = []
+            for l in range(3):          # test-function derivative direction
+                for m in range(3):      # trial-function derivative direction
+                    al = tuple(int(k == m) for k in range(3))
+                    be = tuple(int(k == l) for k in range(3))
+                    terms.append((al, be, K[..., l, m]))
+        else:
+            raise ValueError(which)
+        out = None
+        for al, be, field in terms:
+            T = [self.operator(k, i[k], al[k], be[k]) for k in range(3)]
+            if method == "direct":
+                v = np.einsum("ax,by,cz,xyz->abc", T[0], T[1], T[2], field, optimize=False)
+            elif method == "sumfact":
+                v = field
+                for k in (2, 1, 0):
+                    v = mode_product(v, T[k], k)
+            else:
+                raise ValueError(method)
+            out = v if out is None else out + v
+        # [j1, j2, j3] -> increasing linear column order (j1 fastest)
+        return np.ascontiguousarray(out.transpose(2, 1, 0)).ravel()
+
+    def assemble(self, which: str, method: str = "sumfact") -> np.ndarray:
+        N = self.n[0] * self.n[1] * self.n[2]
+        return np.concatenate([self.row(r, which, method) for r in range(N)])
+
+    # ---- element-wise standard Gauss quadrature (SGQ) -------------------
+    def sgq_matrices(self, which: str, n_gauss: Optional[int] = None) -> np.ndarray:
+        """Dense N x N Galerkin matrix by element-wise Gauss-Legendre quadrature
+        with n_gauss (default p+1) points per direction per element."""
+        ng = self.p + 1 if n_gauss is None else n_gauss
+        gx, gw = np.polynomial.legendre.leggauss(ng)
+        pts, wts = [], []
+        for k in range(3):
+            chi = np.unique(self.knots3[k])
+            P, W = [], []
+            for e in range(len(chi) - 1):
+                a, b = chi[e], chi[e + 1]
+                P.append(0.5 * (a + b) + 0.5 * (b - a) * gx)
+                W.append(0.5 * (b - a) * gw)
+            pts.append(np.concatenate(P))
+            wts.append(np.concatenate(W))
+        F, J = map_and_jacobian(self.knots3, self.p, self.ctrl, pts[0], pts[1], pts[2])
+        a = None if self.coef is None else self.coef(F.reshape(-1, 3)).reshape(F.shape[:3])
+        det, K = coefficients_from_jacobian(J, a)
+        Wq = wts[0][:, None, None] * wts[1][None, :, None] * wts[2][None, None, :]
+        # dense basis tables at Gauss points
+        from .splines import basis_and_derivs
+        tabs = []
+        for k in range(3):
+            V = np.array([basis_and_derivs(list(self.knots3[k]), self.p, float(x))[0] for x in pts[k]])
+            D = np.array([basis_and_derivs(list(self.knots3[k]), self.p, float(x))[1] for x in pts[k]])
+            tabs.append((V.T, D.T))   # (n_k, n_gauss_total)
+        n1, n2, n3 = self.n
+        N = n1 * n2 * n3
+
+        def phi(dirs_deriv):
+            # values of all N tensor basis functions at all points, flattened
+            A = [tabs[k][dirs_deriv[k]] for k in range(3)]
+            T = np.einsum("ix,jy,kz->kjixyz", A[0], A[1], A[2])
+            return T.reshape(N, -1)
+        if which == "mass":
+            P0 = phi((0, 0, 0))
+            return (P0 * (Wq * det).ravel()[None, :]) @ P0.T
+        G = [phi(tuple(int(k == d) for k in range(3))) for d in range(3)]
+        S = np.zeros((N, N))
+        for l in range(3):
+            for m in range(3):
+                S += (G[l] * (Wq * K[..., l, m]).ravel()[None, :]) @ G[m].T
+        return S

@@ -1,0 +1,104 @@
+"""Geometry map and PDE coefficients at points, for the oracle (test
+infrastructure only).
+
+Section 3: the domain is a single spline patch F(zeta) = sum_i C_i B_i(zeta);
+the mass integrand carries c = det DF (eq. mass2) and the stiffness carries
+c_lm = { [DF^{-1} DF^{-T}] det DF }_lm (eq. coef_stiff), here multiplied by a
+scalar diffusion coefficient a(F(zeta)) ("non-constant coefficients could be
+included as well", Section 3).
+
+Everything is evaluated directly from the definition: at each point, the sum
+over the (p+1)^3 tensor-product B-splines that are nonzero there.  The
+inverse is the explicit adjugate formula.
+
+Pins (tests/test_oracle_geometry.py): Greville control points give the
+identity map (J = I, K = I); an affine control net gives J = A everywhere;
+J agrees with central finite differences of F; K agrees with an
+independently computed det(J) inv(J) inv(J)^T (numpy.linalg).
+"""
+from __future__ import annotations
+
+from typing import Optional, Sequence, Tuple
+
+import numpy as np
+
+from .splines import basis_and_derivs, find_span
+
+
+def local_basis(knots: Sequence, p: int, pts: Sequence[float]):
+    """For each point: first index of the p+1 nonzero B-splines, and their
+    values and derivatives there (FP64).  Returns (first[np], V[np,p+1], D[np,p+1])."""
+    knots = [float(k) for k in knots]
+    n = len(knots) - p - 1
+    first = np.zeros(len(pts), dtype=np.int64)
+    V = np.zeros((len(pts), p + 1))
+    D = np.zeros((len(pts), p + 1))
+    for k, x in enumerate(pts):
+        x = float(x)
+        s = find_span(knots, x)
+        vals, ders = basis_and_derivs(knots, p, x)
+        f = min(max(s - p, 0), n - p - 1)
+        first[k] = f
+        V[k] = vals[f:f + p + 1]
+        D[k] = ders[f:f + p + 1]
+    return first, V, D
+
+
+def map_and_jacobian(knots3, p: int, ctrl: np.ndarray, X1, X2, X3):
+    """F and J = dF/dzeta on the tensor grid X1 x X2 x X3.
+
+    ctrl: (n3, n2, n1, 3) control points (linear index i1 + n1(i2 + n2 i3)).
+    Returns F with shape (len(X1), len(X2), len(X3), 3) and J with shape
+    (len(X1), len(X2), len(X3), 3, 3), J[..., a, b] = dF_a / dzeta_b."""
+    f1, V1, D1 = local_basis(knots3[0], p, X1)
+    f2, V2, D2 = local_basis(knots3[1], p, X2)
+    f3, V3, D3 = local_basis(knots3[2], p, X3)
+    r = np.arange(p + 1)
+    n1, n2, n3 = len(X1), len(X2), len(X3)
+    F = np.zeros((n1, n2, n3, 3))
+    J = np.zeros((n1, n2, n3, 3, 3))
+    # gather the local (p+1)^3 control blocks for every grid point
+    i1 = (f1[:, None] + r[None, :])            # (n1, p+1)
+    i2 = (f2[:, None] + r[None, :])
+    i3 = (f3[:, None] + r[None, :])
+    for c in range(n3):                         # one z-plane of points at a time
+        # Cloc[a, b, l3, l2, l1, :] = ctrl[i3[c,l3], i2[b,l2], i1[a,l1], :]
+        Cloc = ctrl[i3[c][None, None, :, None, None],
+                    i2[None, :, None, :, None],
+                    i1[:, None, None, None, :], :]
+        def contract(A1, A2, A3c):
+            # sum over the local functions of the product basis value times C
+            W = (A3c[None, None, :, None, None] * A2[None, :, None, :, None]
+                 * A1[:, None, None, None, :])
+            return np.einsum("abxyz,abxyzd->abd", W, Cloc)
+        F[:, :, c, :] = contract(V1, V2, V3[c])
+        J[:, :, c, :, 0] = contract(D1, V2, V3[c])
+        J[:, :, c, :, 1] = contract(V1, D2, V3[c])
+        J[:, :, c, :, 2] = contract(V1, V2, D3[c])
+    return F, J
+
+
+def coefficients_from_jacobian(J: np.ndarray, a: Optional[np.ndarray] = None):
+    """Mass factor c = det J and stiffness coefficient
+    K = a det(J) J^{-1} J^{-T} = a adj(J) adj(J)^T / det(J) (eq. coef_stiff).
+
+    Returns (detJ[...], K[..., 3, 3])."""
+    j = J
+    c00 = j[..., 1, 1] * j[..., 2, 2] - j[..., 1, 2] * j[..., 2, 1]
+    c01 = j[..., 1, 2] * j[..., 2, 0] - j[..., 1, 0] * j[..., 2, 2]
+    c02 = j[..., 1, 0] * j[..., 2, 1] - j[..., 1, 1] * j[..., 2, 0]
+    c10 = j[..., 0, 2] * j[..., 2, 1] - j[..., 0, 1] * j[..., 2, 2]
+    c11 = j[..., 0, 0] * j[..., 2, 2] - j[..., 0, 2] * j[..., 2, 0]
+    c12 = j[..., 0, 1] * j[..., 2, 0] - j[..., 0, 0] * j[..., 2, 1]
+    c20 = j[..., 0, 1] * j[..., 1, 2] - j[..., 0, 2] * j[..., 1, 1]
+    c21 = j[..., 0, 2] * j[..., 1, 0] - j[..., 0, 0] * j[..., 1, 2]
+    c22 = j[..., 0, 0] * j[..., 1, 1] - j[..., 0, 1] * j[..., 1, 0]
+    det = j[..., 0, 0] * c00 + j[..., 0, 1] * c01 + j[..., 0, 2] * c02
+    # adj(J) = cofactor matrix transposed
+    adj = np.stack([np.stack([c00, c10, c20], -1),
+                    np.stack([c01, c11, c21], -1),
+                    np.stack([c02, c12, c22], -1)], -2)
+    K = np.einsum("...ik,...jk->...ij", adj, adj) / det[..., None, None]
+    if a is not None:
+        K = K * np.asarray(a)[..., None, None]
+    return det, K
