@@ -1,0 +1,211 @@
+/*
+ * wq.h -- C ABI of the MI355X (gfx950) weighted-quadrature matrix-formation
+ * library.
+ *
+ * Method: Calabro, Sangalli, Tani, "Fast formation of isogeometric Galerkin
+ * matrices by weighted quadrature" (arXiv:1605.01238).  The library forms,
+ * row by row, the isogeometric Galerkin mass matrix M~ and stiffness matrix
+ * S~ of the scalar model problem of Section 3 on one 3D tensor-product spline
+ * patch of degree p with maximal continuity C^{p-1}:
+ *   - univariate weighted-quadrature (WQ) rules, four per basis function and
+ *     direction (Section 4, eqs. quadrule/exact/support; Algorithm 2),
+ *   - the integrand coefficients at the global quadrature points (Section 3,
+ *     eqs. mass2, stiff, coef_stiff; Algorithm 1),
+ *   - every row by sum factorization (Section 6, eq. sumfactorization,
+ *     Algorithm 3, and its stiffness analogue), written straight into a CSR
+ *     slot.
+ *
+ * Conventions (all indices 0-based):
+ *   - Direction 1 is fastest: the linear index of (i1, i2, i3) is
+ *     i1 + n1*(i2 + n2*i3) (Section 3).  Row = test function i, column =
+ *     trial function j.  Columns of a row are strictly increasing.  Every
+ *     structurally nonzero pair (supports overlapping, Section 3) is stored,
+ *     even if its value is 0.  No symmetrisation, no boundary conditions.
+ *   - Quadrature points (Remark 4.1): all interior knots, midpoints of the
+ *     internal knot-spans, and in each of the two boundary knot-spans [a,b]
+ *     the p+1 points a + k(b-a)/(p+2), k = 1..p+1 (strictly inside).
+ *     n_qp = 2*n_el + 2*p - 1 per direction.
+ *   - Weight pairing (alpha, beta): beta = derivative order on the test
+ *     function (inside the weight), alpha = derivative order on the trial
+ *     function (the integrand).  The rule is exact:
+ *       sum_q w^(alpha,beta)_{i,q} B_j^(alpha)(x_q) = int B_i^(beta) B_j^(alpha)
+ *     for all j overlapping i, with minimum Euclidean norm (Algorithm 2).
+ *   - Stiffness coefficient at a point: K = a * det(J) * J^{-1} J^{-T}
+ *     (eq. coef_stiff, times the scalar diffusion coefficient a); the mass
+ *     coefficient is det(J) (eq. mass2).
+ *
+ * Memory and streams: the library never allocates device memory.  The
+ * caller allocates one workspace (size from wq_sizes) and all outputs, and
+ * owns them.  Device calls are asynchronous on the given HIP stream
+ * (0 = the legacy default stream).  Host pointers are read before the call
+ * returns.  A plan is a host object; it is not thread-safe; distinct plans
+ * are independent.
+ *
+ * Errors: every call returns a wq_status; nothing is thrown across the ABI.
+ * Host-detectable errors are returned immediately and leave the plan
+ * unchanged.  Device-detected conditions (det J <= 0 at a quadrature point,
+ * a breakdown of a weight solve) are latched in the workspace and reported
+ * by wq_sync.  wq_last_error gives a human-readable message.
+ */
+#ifndef WQ_H
+#define WQ_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct wq_plan wq_plan;
+
+typedef enum {
+  WQ_OK = 0,
+  WQ_EINVAL = -1,     /* bad argument (null pointer, d, p, precision, flags) */
+  WQ_EKNOTS = -2,     /* knot vector not open / not non-decreasing / repeated interior knot / too few spans */
+  WQ_ESINGULAR = -3,  /* a weight system broke down on the device */
+  WQ_EGEOM = -4,      /* det J <= 0 (or not finite) at some quadrature point */
+  WQ_ENOSPACE = -5,   /* workspace smaller than wq_sizes requires, or misaligned */
+  WQ_EDEVICE = -6,    /* a HIP runtime call failed */
+  WQ_ESTATE = -7      /* call order violated (e.g. assemble before setup) */
+} wq_status;
+
+enum { WQ_MASS = 1, WQ_STIFF = 2 };
+enum { WQ_FP64 = 0, WQ_FP32 = 1 };
+
+/* Limits of this build. */
+#define WQ_MIN_P 2
+#define WQ_MAX_P 6
+
+typedef struct {
+  int64_t n[3];          /* basis functions per direction, n_l = n_el,l + p */
+  int64_t n_qp[3];       /* quadrature points per direction */
+  int64_t n_rows;        /* N_DOF = n1 n2 n3 */
+  int64_t nnz;           /* exact nonzeros per matrix (same pattern for M~ and S~) */
+  int64_t n_qp_total;    /* N_QP = n_qp1 n_qp2 n_qp3 */
+  size_t workspace_bytes;/* device workspace the caller must provide */
+  size_t value_bytes;    /* bytes of one value array (nnz * 8 or nnz * 4) */
+} wq_sizes_t;
+
+/*
+ * Create a plan (host only; no device work).
+ *   d          must be 3.
+ *   p          degree, WQ_MIN_P..WQ_MAX_P; the same in every direction.
+ *   n_knots[d] length of each knot vector (n_l + p + 1).
+ *   knots[d]   host pointers to FP64 knot vectors: open (first and last
+ *              p+1 knots equal), non-decreasing, interior knots simple
+ *              (C^{p-1}); at least p+2 knot-spans per direction.  Non-uniform
+ *              spacing is allowed (Section 2).  Copied into the plan.
+ *   precision  WQ_FP64: coefficient field, operators, accumulation and
+ *              values in FP64.  WQ_FP32: the same in FP32 ("FP32 bulk"),
+ *              while weights, det J and J^{-1} are still computed in FP64.
+ *   out        receives the plan (NULL on error).
+ * Errors: WQ_EINVAL, WQ_EKNOTS.
+ */
+wq_status wq_plan_create(int d, int p, const int64_t* n_knots, const double* const* knots,
+                         int precision, wq_plan** out);
+
+/* Sizes of the problem and of the workspace (host only). */
+wq_status wq_sizes(const wq_plan* plan, wq_sizes_t* out);
+
+/* Parametric quadrature-point coordinates of direction dir (0..2) into the
+ * host array x_host[n_qp[dir]] (host only; Remark 4.1). */
+wq_status wq_qpoints(const wq_plan* plan, int dir, double* x_host);
+
+/*
+ * Bind the caller's device workspace (>= workspace_bytes, 256-byte aligned)
+ * to the plan and upload the knot vectors into it (small host-to-device
+ * copy, asynchronous on stream).  Must precede every call below.  Binding a
+ * new workspace invalidates earlier setup.
+ * Errors: WQ_EINVAL, WQ_ENOSPACE, WQ_EDEVICE.
+ */
+wq_status wq_bind(wq_plan* plan, void* workspace, size_t bytes, hipStream_t stream);
+
+/*
+ * Device setup (asynchronous on stream; reads only device memory):
+ *   1. univariate stage for every direction and basis function: B-spline
+ *      values and derivatives at the quadrature points (Algorithm 1), exact
+ *      1D integrals by (p+1)-point Gauss per knot-span (Algorithm 1), and the
+ *      four minimum-norm weight solves (Algorithm 2) in FP64;
+ *   2. geometry stage at every quadrature point: J = dF/dzeta of the spline
+ *      map F(zeta) = sum_i C_i B_i(zeta), det J, and the coefficient field
+ *      (det J; K = a det J J^{-1} J^{-T}) stored in the plan's precision.
+ *   ctrl_dev  device FP64 control points, [n3][n2][n1][3] (i1 fastest,
+ *             physical x,y,z innermost); copied into the workspace, so the
+ *             caller may free it after the call has completed on stream.
+ *   coef_dev  device FP64 array of the diffusion coefficient a at the
+ *             quadrature points, [n_qp3][n_qp2][n_qp1] (q1 fastest), or NULL
+ *             for a = 1.  Read during this call only.
+ * Errors: WQ_EINVAL, WQ_ESTATE, WQ_EDEVICE; det J <= 0 and solve breakdowns
+ * are latched for wq_sync.
+ */
+wq_status wq_setup(wq_plan* plan, const double* ctrl_dev, const double* coef_dev, hipStream_t stream);
+
+/* Recompute only the coefficient field for a new a (same geometry);
+ * coef_dev as in wq_setup.  Requires a prior wq_setup. */
+wq_status wq_set_coefficient(wq_plan* plan, const double* coef_dev, hipStream_t stream);
+
+/* Physical quadrature points F(x_q) into x_dev[n_qp3][n_qp2][n_qp1][3]
+ * (device FP64), e.g. to sample a coefficient a(x).  Requires wq_setup. */
+wq_status wq_qp_physical(const wq_plan* plan, double* x_dev, hipStream_t stream);
+
+/*
+ * CSR pattern (Section 3, sets I_i): row_ptr_dev[n_rows + 1] (int64) and
+ * col_idx_dev[nnz] (int32), both device, caller-owned.  Rows have length
+ * prod_l #I_{l,i_l} with #I = min(n-1, i+p) - max(0, i-p) + 1.  Requires
+ * wq_bind (not wq_setup).
+ */
+wq_status wq_pattern(const wq_plan* plan, int64_t* row_ptr_dev, int32_t* col_idx_dev,
+                     hipStream_t stream);
+
+/*
+ * Form the matrix values into CSR slots (Algorithm 3 and its stiffness
+ * analogue), asynchronous on stream.
+ *   which           WQ_MASS, WQ_STIFF or WQ_MASS|WQ_STIFF.
+ *   mass_vals_dev   device array [nnz] of double (WQ_FP64) or float
+ *                   (WQ_FP32); required iff which has WQ_MASS, else ignored.
+ *   stiff_vals_dev  likewise for WQ_STIFF.
+ * Values are in the order of wq_pattern's col_idx.  Requires wq_setup.
+ * Errors: WQ_EINVAL, WQ_ESTATE, WQ_EDEVICE.
+ */
+wq_status wq_assemble(wq_plan* plan, int which, void* mass_vals_dev, void* stiff_vals_dev,
+                      hipStream_t stream);
+
+/*
+ * Export intermediate products for inspection/testing (device, asynchronous):
+ *   wq_weights: the FP64 weights of direction dir and pairing index
+ *     pair = 2*beta + alpha for (alpha, beta) in {(0,0),(1,0),(0,1),(1,1)},
+ *     as w_dev[n][qcap] with w_dev[i][k] the weight at quadrature point
+ *     q_start(i) + k (zero beyond #Q_i); q_start_dev[n], q_count_dev[n]
+ *     (int32) give Q_i.  qcap = 3p+1.
+ *   wq_field: the coefficient field in the plan's precision, as
+ *     field_dev[7][n_qp3][n_qp2][n_qp1] with channels
+ *     (det J, K11, K22, K33, K12, K13, K23).
+ */
+wq_status wq_weights(const wq_plan* plan, int dir, int pair, double* w_dev, int32_t* q_start_dev,
+                     int32_t* q_count_dev, hipStream_t stream);
+wq_status wq_field(const wq_plan* plan, void* field_dev, hipStream_t stream);
+
+/*
+ * Wait for all work of the plan on stream, then report latched device
+ * conditions (and clear them): WQ_EGEOM if det J <= 0 somewhere,
+ * WQ_ESINGULAR if a weight solve broke down, WQ_EDEVICE on a runtime error.
+ */
+wq_status wq_sync(wq_plan* plan, hipStream_t stream);
+
+/* Message for the last error of this plan (never NULL; "" if none). */
+const char* wq_last_error(const wq_plan* plan);
+
+/* Free the plan (host memory only; the caller frees its device buffers). */
+void wq_plan_destroy(wq_plan* plan);
+
+/* Library version string. */
+const char* wq_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* WQ_H */

@@ -87,15 +87,34 @@ class Problem:
         Bt = self.B[k][alpha][np.ix_(r.I[ik], r.Q[ik])]
         return Bt * r.w64[(alpha, beta)][ik][None, :]
 
-    def row_fields(self, row: int):
-        """Coefficients on the block Q_i1 x Q_i2 x Q_i3 (arrays indexed
-        [q1, q2, q3]): mass factor det J, stiffness K (3x3), and F."""
-        i = self.multi(row)
-        X = [self.rules[k].x64[self.rules[k].Q[i[k]]] for k in range(3)]
+    GRID_LIMIT = 100_000   # quadrature grids up to this size are evaluated once
+
+    def _fields_on(self, X):
         F, J = map_and_jacobian(self.knots3, self.p, self.ctrl, X[0], X[1], X[2])
+        F = F.astype(np.float64)
         a = None if self.coef is None else self.coef(F.reshape(-1, 3)).reshape(F.shape[:3])
         det, K = coefficients_from_jacobian(J, a)
-        return det, K, F
+        return det.astype(np.float64), K.astype(np.float64), F
+
+    def row_fields(self, row: int):
+        """Coefficients on the block Q_i1 x Q_i2 x Q_i3 (arrays indexed
+        [q1, q2, q3]): mass factor det J, stiffness K (3x3), and F, evaluated
+        at the exact quadrature points (on the whole grid at once when it is
+        small, else on the row's block)."""
+        i = self.multi(row)
+        Q = [self.rules[k].Q[i[k]] for k in range(3)]
+        last = getattr(self, "_last", None)
+        if last is not None and last[0] == row:
+            return last[1]
+        if np.prod([len(r.x) for r in self.rules]) <= self.GRID_LIMIT:
+            if getattr(self, "_grid", None) is None:
+                self._grid = self._fields_on([r.x for r in self.rules])
+            det, K, F = self._grid
+            s = tuple(slice(q[0], q[-1] + 1) for q in Q)
+            return det[s], K[s], F[s]
+        out = self._fields_on([[self.rules[k].x[q] for q in Q[k]] for k in range(3)])
+        self._last = (row, out)
+        return out
 
     # ---- formation ---------------------------------------------------------
     def row(self, row: int, which: str, method: str = "sumfact") -> np.ndarray:
@@ -149,8 +168,10 @@ class Problem:
             pts.append(np.concatenate(P))
             wts.append(np.concatenate(W))
         F, J = map_and_jacobian(self.knots3, self.p, self.ctrl, pts[0], pts[1], pts[2])
+        F = F.astype(np.float64)
         a = None if self.coef is None else self.coef(F.reshape(-1, 3)).reshape(F.shape[:3])
         det, K = coefficients_from_jacobian(J, a)
+        det, K = det.astype(np.float64), K.astype(np.float64)
         Wq = wts[0][:, None, None] * wts[1][None, :, None] * wts[2][None, None, :]
         # dense basis tables at Gauss points
         from .splines import basis_and_derivs

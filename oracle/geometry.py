@@ -11,6 +11,13 @@ Everything is evaluated directly from the definition: at each point, the sum
 over the (p+1)^3 tensor-product B-splines that are nonzero there.  The
 inverse is the explicit adjugate formula.
 
+Precision: DF = sum_i C_i grad B_i cancels strongly (the B_i' sum to zero and
+are O(1/h)), so a plain FP64 evaluation carries O(eps/h) error.  To serve as
+a reference, the oracle evaluates the same sums in x87 extended precision
+(numpy longdouble, 64-bit significand); at rational points (the quadrature
+points) the univariate B-spline values and derivatives are exact rationals
+before conversion.  Results are rounded to FP64 by the callers.
+
 Pins (tests/test_oracle_geometry.py): Greville control points give the
 identity map (J = I, K = I); an affine control net gives J = A everywhere;
 J agrees with central finite differences of F; K agrees with an
@@ -22,25 +29,42 @@ from typing import Optional, Sequence, Tuple
 
 import numpy as np
 
-from .splines import basis_and_derivs, find_span
+from fractions import Fraction
+
+from .splines import basis_and_derivs, exact_knots, find_span
 
 
-def local_basis(knots: Sequence, p: int, pts: Sequence[float]):
+LD = np.longdouble
+
+
+def to_ld(v) -> np.longdouble:
+    """A float or an exact Fraction as longdouble (two-term split of a
+    Fraction, so the conversion is correctly rounded to 64 bits)."""
+    if isinstance(v, Fraction):
+        hi = float(v)
+        return LD(hi) + LD(float(v - Fraction(hi)))
+    return LD(v)
+
+
+def local_basis(knots: Sequence, p: int, pts: Sequence):
     """For each point: first index of the p+1 nonzero B-splines, and their
-    values and derivatives there (FP64).  Returns (first[np], V[np,p+1], D[np,p+1])."""
-    knots = [float(k) for k in knots]
-    n = len(knots) - p - 1
+    values and derivatives there.  Points given as Fractions are evaluated
+    exactly (exact knots); floats in FP64.  Returns (first[np], V[np,p+1],
+    D[np,p+1]) with V, D in longdouble."""
+    exact = len(pts) > 0 and isinstance(pts[0], Fraction)
+    kn = exact_knots(knots) if exact else [float(k) for k in knots]
+    n = len(kn) - p - 1
     first = np.zeros(len(pts), dtype=np.int64)
-    V = np.zeros((len(pts), p + 1))
-    D = np.zeros((len(pts), p + 1))
+    V = np.zeros((len(pts), p + 1), dtype=LD)
+    D = np.zeros((len(pts), p + 1), dtype=LD)
     for k, x in enumerate(pts):
-        x = float(x)
-        s = find_span(knots, x)
-        vals, ders = basis_and_derivs(knots, p, x)
+        x = x if exact else float(x)
+        s = find_span(kn, x)
+        vals, ders = basis_and_derivs(kn, p, x)
         f = min(max(s - p, 0), n - p - 1)
         first[k] = f
-        V[k] = vals[f:f + p + 1]
-        D[k] = ders[f:f + p + 1]
+        V[k] = [to_ld(t) for t in vals[f:f + p + 1]]
+        D[k] = [to_ld(t) for t in ders[f:f + p + 1]]
     return first, V, D
 
 
@@ -49,14 +73,16 @@ def map_and_jacobian(knots3, p: int, ctrl: np.ndarray, X1, X2, X3):
 
     ctrl: (n3, n2, n1, 3) control points (linear index i1 + n1(i2 + n2 i3)).
     Returns F with shape (len(X1), len(X2), len(X3), 3) and J with shape
-    (len(X1), len(X2), len(X3), 3, 3), J[..., a, b] = dF_a / dzeta_b."""
+    (len(X1), len(X2), len(X3), 3, 3), J[..., a, b] = dF_a / dzeta_b, in
+    longdouble."""
+    ctrl = np.asarray(ctrl).astype(LD)
     f1, V1, D1 = local_basis(knots3[0], p, X1)
     f2, V2, D2 = local_basis(knots3[1], p, X2)
     f3, V3, D3 = local_basis(knots3[2], p, X3)
     r = np.arange(p + 1)
     n1, n2, n3 = len(X1), len(X2), len(X3)
-    F = np.zeros((n1, n2, n3, 3))
-    J = np.zeros((n1, n2, n3, 3, 3))
+    F = np.zeros((n1, n2, n3, 3), dtype=LD)
+    J = np.zeros((n1, n2, n3, 3, 3), dtype=LD)
     # gather the local (p+1)^3 control blocks for every grid point
     i1 = (f1[:, None] + r[None, :])            # (n1, p+1)
     i2 = (f2[:, None] + r[None, :])

@@ -1,0 +1,125 @@
+"""Weighted-quadrature formation of isogeometric Galerkin matrices on MI355X.
+
+``Plan`` is a thin convenience wrapper over the C-ABI (include/wq.h, bound in
+``_wq``): it allocates the device workspace and the CSR outputs with PyTorch
+(device memory and streams only) and forwards every call to libwq.so.
+"""
+from __future__ import annotations
+
+import ctypes as C
+from typing import Optional, Sequence
+
+import numpy as np
+
+from . import _wq
+from ._wq import (WQ_FP32, WQ_FP64, WQ_MASS, WQ_STIFF, WQError, check)
+
+__all__ = ["Plan", "WQError", "WQ_FP32", "WQ_FP64", "WQ_MASS", "WQ_STIFF"]
+
+
+def _ptr(t) -> Optional[int]:
+    return None if t is None else t.data_ptr()
+
+
+def _stream(stream) -> Optional[int]:
+    import torch
+    s = torch.cuda.current_stream() if stream is None else stream
+    return s.cuda_stream
+
+
+class Plan:
+    """One 3D single-patch problem on the current CUDA (HIP) device."""
+
+    def __init__(self, knots3: Sequence[np.ndarray], p: int, precision: int = WQ_FP64):
+        self._h = C.c_void_p()
+        ks = [np.ascontiguousarray(k, dtype=np.float64) for k in knots3]
+        self._keep = ks
+        n_knots = (C.c_int64 * len(ks))(*[len(k) for k in ks])
+        ptrs = (C.POINTER(C.c_double) * len(ks))(*[k.ctypes.data_as(C.POINTER(C.c_double)) for k in ks])
+        check(_wq.wq_plan_create(len(ks), p, n_knots, ptrs, precision, C.byref(self._h)))
+        self.p = p
+        self.precision = precision
+        s = _wq.wq_sizes_t()
+        check(_wq.wq_sizes(self._h, C.byref(s)), self._h)
+        self.sizes = s
+        self.n = tuple(s.n)
+        self.n_qp = tuple(s.n_qp)
+        self.n_rows = s.n_rows
+        self.nnz = s.nnz
+        self.n_qp_total = s.n_qp_total
+        self.workspace = None
+
+    @property
+    def value_dtype(self):
+        import torch
+        return torch.float64 if self.precision == WQ_FP64 else torch.float32
+
+    def qpoints(self, d: int) -> np.ndarray:
+        x = np.zeros(self.n_qp[d], dtype=np.float64)
+        check(_wq.wq_qpoints(self._h, d, x.ctypes.data_as(C.POINTER(C.c_double))), self._h)
+        return x
+
+    def bind(self, stream=None, workspace=None):
+        import torch
+        if workspace is None:
+            workspace = torch.empty(self.sizes.workspace_bytes + 256, dtype=torch.uint8, device="cuda")
+        off = (-workspace.data_ptr()) % 256
+        self.workspace = workspace
+        check(_wq.wq_bind(self._h, workspace.data_ptr() + off, workspace.numel() - off, _stream(stream)), self._h)
+
+    def setup(self, ctrl, coef=None, stream=None):
+        """ctrl: device float64 tensor (n3, n2, n1, 3); coef: device float64
+        tensor with n_qp_total entries (q1 fastest) or None for a = 1."""
+        check(_wq.wq_setup(self._h, _ptr(ctrl), _ptr(coef), _stream(stream)), self._h)
+
+    def set_coefficient(self, coef, stream=None):
+        check(_wq.wq_set_coefficient(self._h, _ptr(coef), _stream(stream)), self._h)
+
+    def qp_physical(self, stream=None):
+        import torch
+        x = torch.empty((self.n_qp[2], self.n_qp[1], self.n_qp[0], 3), dtype=torch.float64, device="cuda")
+        check(_wq.wq_qp_physical(self._h, _ptr(x), _stream(stream)), self._h)
+        return x
+
+    def pattern(self, row_ptr=None, col_idx=None, stream=None):
+        import torch
+        if row_ptr is None:
+            row_ptr = torch.empty(self.n_rows + 1, dtype=torch.int64, device="cuda")
+        if col_idx is None:
+            col_idx = torch.empty(self.nnz, dtype=torch.int32, device="cuda")
+        check(_wq.wq_pattern(self._h, _ptr(row_ptr), _ptr(col_idx), _stream(stream)), self._h)
+        return row_ptr, col_idx
+
+    def assemble(self, which: int, mass=None, stiff=None, stream=None):
+        import torch
+        if (which & WQ_MASS) and mass is None:
+            mass = torch.empty(self.nnz, dtype=self.value_dtype, device="cuda")
+        if (which & WQ_STIFF) and stiff is None:
+            stiff = torch.empty(self.nnz, dtype=self.value_dtype, device="cuda")
+        check(_wq.wq_assemble(self._h, which, _ptr(mass) if which & WQ_MASS else None,
+                              _ptr(stiff) if which & WQ_STIFF else None, _stream(stream)), self._h)
+        return mass, stiff
+
+    def weights(self, d: int, pair: int, stream=None):
+        import torch
+        qcap = 3 * self.p + 1
+        w = torch.empty((self.n[d], qcap), dtype=torch.float64, device="cuda")
+        qs = torch.empty(self.n[d], dtype=torch.int32, device="cuda")
+        qc = torch.empty(self.n[d], dtype=torch.int32, device="cuda")
+        check(_wq.wq_weights(self._h, d, pair, _ptr(w), _ptr(qs), _ptr(qc), _stream(stream)), self._h)
+        return w, qs, qc
+
+    def field(self, stream=None):
+        import torch
+        f = torch.empty((7, self.n_qp[2], self.n_qp[1], self.n_qp[0]), dtype=self.value_dtype, device="cuda")
+        check(_wq.wq_field(self._h, _ptr(f), _stream(stream)), self._h)
+        return f
+
+    def sync(self, stream=None):
+        check(_wq.wq_sync(self._h, _stream(stream)), self._h)
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            _wq.wq_plan_destroy(h)
+            self._h = C.c_void_p()

@@ -1,0 +1,116 @@
+// Internal declarations of the weighted-quadrature library (not part of the ABI).
+//
+// Index conventions follow include/wq.h.  Per direction, with n_el knot-spans
+// (distinct knots chi_0 < ... < chi_{n_el}), n = n_el + p basis functions and
+// the quadrature points of Remark 4.1 numbered left to right:
+//   q = 0..p                  : p+1 points inside the first span,
+//   q = p + 2k - 1, k=1..n_el-1 : interior knot chi_k,
+//   q = p + 2k,     k=1..n_el-2 : midpoint of the internal span k,
+//   q = p + 2 n_el - 2 + t, t=0..p : p+1 points inside the last span.
+// n_qp = 2 n_el + 2p - 1.  B_i is supported on the spans e in
+// [max(0, i-p), min(n_el, i+1)); Q_i is the contiguous range of points
+// strictly inside that support; I_i = [max(0, i-p), min(n-1, i+p)].
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/wq.h"
+
+namespace wq {
+
+constexpr int kNumChannels = 7;   // det J, K11, K22, K33, K12, K13, K23
+constexpr int kNumFlags = 16;
+
+// Latched device conditions (int32 counters in the workspace).
+enum Flag : int {
+  FLAG_DETJ_BAD = 0,      // count of quadrature points with det J <= 0 or not finite
+  FLAG_DETJ_FIRST = 1,    // smallest offending linear quadrature-point index (atomicMin)
+  FLAG_SOLVE_BAD = 2,     // count of weight systems that broke down
+  FLAG_SOLVE_FIRST = 3,   // first offending (dir*4 + pair) * n + i
+};
+
+__host__ __device__ inline int qcap_of(int p) { return 3 * p + 1; }
+__host__ __device__ inline int icap_of(int p) { return 2 * p + 1; }
+
+__host__ __device__ inline int span_first_q(int e, int p, int nel) {
+  return e == 0 ? 0 : (e <= nel - 2 ? p + 2 * e : p + 2 * nel - 2);
+}
+__host__ __device__ inline int span_last_q(int e, int p, int nel) {
+  return e == 0 ? p : (e <= nel - 2 ? p + 2 * e : 2 * nel + 2 * p - 2);
+}
+// Q_i = [qs, qs + qc)
+__host__ __device__ inline void q_range(int i, int p, int nel, int& qs, int& qc) {
+  int e0 = i - p > 0 ? i - p : 0;
+  int e1 = i + 1 < nel ? i + 1 : nel;
+  qs = span_first_q(e0, p, nel);
+  qc = span_last_q(e1 - 1, p, nel) - qs + 1;
+}
+// I_i = [is, is + ic)
+__host__ __device__ inline void i_range(int i, int p, int n, int& is, int& ic) {
+  is = i - p > 0 ? i - p : 0;
+  int ie = i + p < n - 1 ? i + p : n - 1;
+  ic = ie - is + 1;
+}
+
+// Device views (passed by value to kernels).
+struct DirView {
+  int n, nel, nq;
+  const double* knots;   // n + p + 1
+  double* x;             // nq   quadrature points
+  int32_t* qspan;        // nq   first nonzero function at x_q (= distinct-span index)
+  double* bv;            // nq * (p+1) values of functions qspan..qspan+p at x_q
+  double* bd;            // nq * (p+1) derivatives
+  double* bw;            // nq * p  p N_{i,p-1}(x_q) / (xi_{i+p} - xi_i), i = qspan+1 .. qspan+p
+  double* w;             // 4 * n * qcap   weights, pair = 2*beta + alpha
+  double* op64;          // 4 * n * icap * qcap   T[j][q] = B^(alpha)_j(x_q) w_q
+  float* op32;           // same in FP32
+  double* bt64;          // 2 * n * icap * qcap   B^(alpha)_{is+jj}(x_{qs+qq})
+  float* bt32;
+  int64_t* prefix;       // n + 1  prefix sums of #I_i
+};
+
+struct PlanView {
+  int p;
+  int prec;
+  DirView dir[3];
+  void* field;           // kNumChannels * nqtot in the plan precision
+  double* ctrl;          // n3*n2*n1*3
+  double* dctrl;         // 3 * n3*n2*n1*3: C_i - C_{i - e_b} along direction b (0 where i_b = 0)
+  int32_t* flags;        // kNumFlags
+  int64_t nqtot;
+};
+
+struct Layout {
+  size_t knots[3], x[3], qspan[3], bv[3], bd[3], bw[3], w[3], op64[3], op32[3], bt64[3], bt32[3], prefix[3];
+  size_t field, ctrl, dctrl, flags, total;
+};
+
+}  // namespace wq
+
+struct wq_plan {
+  int d = 3, p = 0, prec = 0;
+  int64_t n[3] = {0, 0, 0}, nel[3] = {0, 0, 0}, nq[3] = {0, 0, 0};
+  std::vector<double> knots[3];
+  int64_t nrows = 0, nnz = 0, nqtot = 0;
+  wq::Layout lay{};
+  char* ws = nullptr;
+  size_t ws_bytes = 0;
+  bool bound = false, setup_done = false;
+  std::string err;
+  wq::PlanView view() const;
+};
+
+namespace wq {
+// Kernel launchers (return hipError_t of the launch).
+hipError_t launch_points(const PlanView& v, hipStream_t s);
+hipError_t launch_rules(const PlanView& v, hipStream_t s);
+hipError_t launch_ctrl_diff(const PlanView& v, hipStream_t s);
+hipError_t launch_geometry(const PlanView& v, const double* coef, double* xphys_out, hipStream_t s);
+hipError_t launch_pattern(const PlanView& v, int64_t* row_ptr, int32_t* col_idx, hipStream_t s);
+hipError_t launch_assemble(const PlanView& v, int which, void* mass, void* stiff, hipStream_t s);
+}  // namespace wq

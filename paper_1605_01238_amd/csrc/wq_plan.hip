@@ -1,0 +1,320 @@
+// C ABI entry points: plan validation, sizes, workspace layout, and the
+// ordering of the device stages.  See include/wq.h for the contract.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+
+#include "wq_internal.h"
+
+namespace {
+
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+wq_status fail(wq_plan* plan, wq_status st, const std::string& msg) {
+  if (plan) plan->err = msg;
+  return st;
+}
+
+wq_status hip_fail(wq_plan* plan, hipError_t e, const char* where) {
+  std::string m = std::string(where) + ": " + hipGetErrorString(e);
+  return fail(plan, WQ_EDEVICE, m);
+}
+
+// Validates one knot vector; returns "" if fine.
+std::string check_knots(const double* k, int64_t len, int p, int64_t* nel_out) {
+  if (len < 2 * (p + 1) + 1) return "knot vector too short";
+  for (int64_t i = 0; i < len; ++i)
+    if (!std::isfinite(k[i])) return "non-finite knot";
+  for (int64_t i = 0; i + 1 < len; ++i)
+    if (k[i + 1] < k[i]) return "knots must be non-decreasing";
+  for (int i = 1; i <= p; ++i)
+    if (k[i] != k[0] || k[len - 1 - i] != k[len - 1]) return "knot vector must be open (end knots repeated p+1 times)";
+  if (!(k[p + 1] > k[p]) || !(k[len - 1 - p] > k[len - 2 - p])) return "knot vector must be open (end knots repeated exactly p+1 times)";
+  for (int64_t i = p + 1; i + 1 < len - p; ++i)
+    if (!(k[i + 1] > k[i])) return "interior knots must be simple (maximal regularity C^{p-1})";
+  int64_t nel = len - 2 * p - 1;
+  if (nel < p + 2) return "need at least p+2 knot-spans per direction";
+  *nel_out = nel;
+  return "";
+}
+
+void compute_layout(wq_plan* pl) {
+  wq::Layout& L = pl->lay;
+  size_t off = 0;
+  const int p = pl->p, qc = wq::qcap_of(p), ic = wq::icap_of(p);
+  auto take = [&](size_t bytes) { size_t o = off; off = align256(off + bytes); return o; };
+  for (int k = 0; k < 3; ++k) {
+    const size_t n = size_t(pl->n[k]), nq = size_t(pl->nq[k]);
+    L.knots[k] = take((n + p + 1) * 8);
+    L.x[k] = take(nq * 8);
+    L.qspan[k] = take(nq * 4);
+    L.bv[k] = take(nq * (p + 1) * 8);
+    L.bd[k] = take(nq * (p + 1) * 8);
+    L.bw[k] = take(nq * p * 8);
+    L.w[k] = take(4 * n * qc * 8);
+    L.op64[k] = take(4 * n * ic * qc * 8);
+    L.op32[k] = take(4 * n * ic * qc * 4);
+    L.bt64[k] = take(2 * n * ic * qc * 8);
+    L.bt32[k] = take(2 * n * ic * qc * 4);
+    L.prefix[k] = take((n + 1) * 8);
+  }
+  L.field = take(size_t(wq::kNumChannels) * size_t(pl->nqtot) * (pl->prec == WQ_FP64 ? 8 : 4));
+  L.ctrl = take(size_t(pl->nrows) * 3 * 8);
+  L.dctrl = take(size_t(pl->nrows) * 9 * 8);
+  L.flags = take(wq::kNumFlags * 4);
+  L.total = off;
+}
+
+}  // namespace
+
+wq::PlanView wq_plan::view() const {
+  wq::PlanView v{};
+  v.p = p;
+  v.prec = prec;
+  for (int k = 0; k < 3; ++k) {
+    wq::DirView& d = v.dir[k];
+    d.n = int(n[k]);
+    d.nel = int(nel[k]);
+    d.nq = int(nq[k]);
+    d.knots = reinterpret_cast<const double*>(ws + lay.knots[k]);
+    d.x = reinterpret_cast<double*>(ws + lay.x[k]);
+    d.qspan = reinterpret_cast<int32_t*>(ws + lay.qspan[k]);
+    d.bv = reinterpret_cast<double*>(ws + lay.bv[k]);
+    d.bd = reinterpret_cast<double*>(ws + lay.bd[k]);
+    d.bw = reinterpret_cast<double*>(ws + lay.bw[k]);
+    d.w = reinterpret_cast<double*>(ws + lay.w[k]);
+    d.op64 = reinterpret_cast<double*>(ws + lay.op64[k]);
+    d.op32 = reinterpret_cast<float*>(ws + lay.op32[k]);
+    d.bt64 = reinterpret_cast<double*>(ws + lay.bt64[k]);
+    d.bt32 = reinterpret_cast<float*>(ws + lay.bt32[k]);
+    d.prefix = reinterpret_cast<int64_t*>(ws + lay.prefix[k]);
+  }
+  v.field = ws + lay.field;
+  v.ctrl = reinterpret_cast<double*>(ws + lay.ctrl);
+  v.dctrl = reinterpret_cast<double*>(ws + lay.dctrl);
+  v.flags = reinterpret_cast<int32_t*>(ws + lay.flags);
+  v.nqtot = nqtot;
+  return v;
+}
+
+extern "C" {
+
+const char* wq_version(void) { return "wq-gfx950 0.1"; }
+
+wq_status wq_plan_create(int d, int p, const int64_t* n_knots, const double* const* knots,
+                         int precision, wq_plan** out) {
+  if (!out) return WQ_EINVAL;
+  *out = nullptr;
+  if (d != 3 || p < WQ_MIN_P || p > WQ_MAX_P || !n_knots || !knots) return WQ_EINVAL;
+  if (precision != WQ_FP64 && precision != WQ_FP32) return WQ_EINVAL;
+  wq_plan* pl = new (std::nothrow) wq_plan();
+  if (!pl) return WQ_EINVAL;
+  pl->d = d;
+  pl->p = p;
+  pl->prec = precision;
+  int64_t nrows = 1, nnz = 1, nqtot = 1;
+  for (int k = 0; k < 3; ++k) {
+    if (!knots[k] || n_knots[k] <= 0 || n_knots[k] > (int64_t(1) << 24)) { delete pl; return WQ_EINVAL; }
+    int64_t nel = 0;
+    std::string msg = check_knots(knots[k], n_knots[k], p, &nel);
+    if (!msg.empty()) { delete pl; return WQ_EKNOTS; }
+    pl->knots[k].assign(knots[k], knots[k] + n_knots[k]);
+    pl->nel[k] = nel;
+    pl->n[k] = nel + p;
+    pl->nq[k] = 2 * nel + 2 * p - 1;
+    nrows *= pl->n[k];
+    nnz *= (2 * p + 1) * pl->n[k] - p * (p + 1);   // Section 3, 1D count; tensor product
+    nqtot *= pl->nq[k];
+  }
+  // 32-bit index limits of the kernels: column and quadrature-point indices.
+  if (nrows >= (int64_t(1) << 31) || nqtot >= (int64_t(1) << 31)) { delete pl; return WQ_EINVAL; }
+  pl->nrows = nrows;
+  pl->nnz = nnz;
+  pl->nqtot = nqtot;
+  compute_layout(pl);
+  *out = pl;
+  return WQ_OK;
+}
+
+wq_status wq_sizes(const wq_plan* plan, wq_sizes_t* out) {
+  if (!plan || !out) return WQ_EINVAL;
+  for (int k = 0; k < 3; ++k) {
+    out->n[k] = plan->n[k];
+    out->n_qp[k] = plan->nq[k];
+  }
+  out->n_rows = plan->nrows;
+  out->nnz = plan->nnz;
+  out->n_qp_total = plan->nqtot;
+  out->workspace_bytes = plan->lay.total;
+  out->value_bytes = size_t(plan->nnz) * (plan->prec == WQ_FP64 ? 8 : 4);
+  return WQ_OK;
+}
+
+wq_status wq_qpoints(const wq_plan* plan, int dir, double* x) {
+  if (!plan || !x || dir < 0 || dir > 2) return WQ_EINVAL;
+  const int p = plan->p;
+  const int nel = int(plan->nel[dir]);
+  const double* k = plan->knots[dir].data();
+  for (int q = 0; q < plan->nq[dir]; ++q) {
+    double v;
+    if (q <= p) {
+      v = k[p] + (q + 1) * ((k[p + 1] - k[p]) / (p + 2));
+    } else if (q >= p + 2 * nel - 2) {
+      const int t = q - (p + 2 * nel - 2);
+      v = k[p + nel - 1] + (t + 1) * ((k[p + nel] - k[p + nel - 1]) / (p + 2));
+    } else {
+      const int m = q - p;
+      v = (m & 1) ? k[p + (m + 1) / 2] : 0.5 * (k[p + m / 2] + k[p + m / 2 + 1]);
+    }
+    x[q] = v;
+  }
+  return WQ_OK;
+}
+
+wq_status wq_bind(wq_plan* plan, void* workspace, size_t bytes, hipStream_t stream) {
+  if (!plan || !workspace) return fail(plan, WQ_EINVAL, "null workspace");
+  if (bytes < plan->lay.total) return fail(plan, WQ_ENOSPACE, "workspace smaller than wq_sizes().workspace_bytes");
+  if (reinterpret_cast<uintptr_t>(workspace) % 256 != 0) return fail(plan, WQ_ENOSPACE, "workspace must be 256-byte aligned");
+  plan->ws = static_cast<char*>(workspace);
+  plan->ws_bytes = bytes;
+  plan->bound = true;
+  plan->setup_done = false;
+  for (int k = 0; k < 3; ++k) {
+    hipError_t e = hipMemcpyAsync(plan->ws + plan->lay.knots[k], plan->knots[k].data(),
+                                  plan->knots[k].size() * 8, hipMemcpyHostToDevice, stream);
+    if (e != hipSuccess) return hip_fail(plan, e, "wq_bind: knot upload");
+  }
+  hipError_t e = hipMemsetAsync(plan->ws + plan->lay.flags, 0, wq::kNumFlags * 4, stream);
+  if (e != hipSuccess) return hip_fail(plan, e, "wq_bind: flag reset");
+  // FLAG_DETJ_FIRST / FLAG_SOLVE_FIRST start at INT_MAX (atomicMin targets).
+  static const int32_t init[2] = {0x7fffffff, 0x7fffffff};
+  e = hipMemcpyAsync(plan->ws + plan->lay.flags + 4 * wq::FLAG_DETJ_FIRST, &init[0], 4, hipMemcpyHostToDevice, stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(plan->ws + plan->lay.flags + 4 * wq::FLAG_SOLVE_FIRST, &init[1], 4, hipMemcpyHostToDevice, stream);
+  if (e != hipSuccess) return hip_fail(plan, e, "wq_bind: flag init");
+  e = wq::launch_points(plan->view(), stream);
+  if (e != hipSuccess) return hip_fail(plan, e, "wq_bind: points kernel");
+  plan->err.clear();
+  return WQ_OK;
+}
+
+wq_status wq_setup(wq_plan* plan, const double* ctrl_dev, const double* coef_dev, hipStream_t stream) {
+  if (!plan) return WQ_EINVAL;
+  if (!plan->bound) return fail(plan, WQ_ESTATE, "wq_setup before wq_bind");
+  if (!ctrl_dev) return fail(plan, WQ_EINVAL, "null control net");
+  hipError_t e = hipMemcpyAsync(plan->ws + plan->lay.ctrl, ctrl_dev, size_t(plan->nrows) * 3 * 8,
+                                hipMemcpyDeviceToDevice, stream);
+  if (e != hipSuccess) return hip_fail(plan, e, "wq_setup: control net copy");
+  wq::PlanView v = plan->view();
+  e = wq::launch_ctrl_diff(v, stream);
+  if (e != hipSuccess) return hip_fail(plan, e, "wq_setup: control-net differences");
+  e = wq::launch_rules(v, stream);
+  if (e != hipSuccess) return hip_fail(plan, e, "wq_setup: univariate kernel");
+  e = wq::launch_geometry(v, coef_dev, nullptr, stream);
+  if (e != hipSuccess) return hip_fail(plan, e, "wq_setup: geometry kernel");
+  plan->setup_done = true;
+  return WQ_OK;
+}
+
+wq_status wq_set_coefficient(wq_plan* plan, const double* coef_dev, hipStream_t stream) {
+  if (!plan) return WQ_EINVAL;
+  if (!plan->setup_done) return fail(plan, WQ_ESTATE, "wq_set_coefficient before wq_setup");
+  hipError_t e = wq::launch_geometry(plan->view(), coef_dev, nullptr, stream);
+  if (e != hipSuccess) return hip_fail(plan, e, "wq_set_coefficient: geometry kernel");
+  return WQ_OK;
+}
+
+wq_status wq_qp_physical(const wq_plan* plan, double* x_dev, hipStream_t stream) {
+  if (!plan || !x_dev) return WQ_EINVAL;
+  if (!plan->setup_done) return WQ_ESTATE;
+  hipError_t e = wq::launch_geometry(plan->view(), nullptr, x_dev, stream);
+  return e == hipSuccess ? WQ_OK : WQ_EDEVICE;
+}
+
+wq_status wq_pattern(const wq_plan* plan, int64_t* row_ptr, int32_t* col_idx, hipStream_t stream) {
+  if (!plan || !row_ptr || !col_idx) return WQ_EINVAL;
+  if (!plan->bound) return WQ_ESTATE;
+  hipError_t e = wq::launch_pattern(plan->view(), row_ptr, col_idx, stream);
+  return e == hipSuccess ? WQ_OK : WQ_EDEVICE;
+}
+
+wq_status wq_assemble(wq_plan* plan, int which, void* mass, void* stiff, hipStream_t stream) {
+  if (!plan) return WQ_EINVAL;
+  if (which <= 0 || (which & ~(WQ_MASS | WQ_STIFF))) return fail(plan, WQ_EINVAL, "which must be WQ_MASS, WQ_STIFF or both");
+  if ((which & WQ_MASS) && !mass) return fail(plan, WQ_EINVAL, "null mass output");
+  if ((which & WQ_STIFF) && !stiff) return fail(plan, WQ_EINVAL, "null stiffness output");
+  if (!plan->setup_done) return fail(plan, WQ_ESTATE, "wq_assemble before wq_setup");
+  hipError_t e = wq::launch_assemble(plan->view(), which, mass, stiff, stream);
+  if (e != hipSuccess) return hip_fail(plan, e, "wq_assemble: contraction kernel");
+  return WQ_OK;
+}
+
+wq_status wq_weights(const wq_plan* plan, int dir, int pair, double* w_dev, int32_t* qs_dev,
+                     int32_t* qc_dev, hipStream_t stream) {
+  if (!plan || dir < 0 || dir > 2 || pair < 0 || pair > 3 || !w_dev) return WQ_EINVAL;
+  if (!plan->setup_done) return WQ_ESTATE;
+  const int p = plan->p, n = int(plan->n[dir]), qc = wq::qcap_of(p);
+  const size_t bytes = size_t(n) * qc * 8;
+  hipError_t e = hipMemcpyAsync(w_dev, plan->ws + plan->lay.w[dir] + size_t(pair) * bytes, bytes,
+                                hipMemcpyDeviceToDevice, stream);
+  if (e != hipSuccess) return WQ_EDEVICE;
+  if (qs_dev || qc_dev) {
+    std::vector<int32_t> s(n), c(n);
+    for (int i = 0; i < n; ++i) {
+      int a, b;
+      wq::q_range(i, p, int(plan->nel[dir]), a, b);
+      s[i] = a;
+      c[i] = b;
+    }
+    // synchronous copies from pageable memory: the vectors die with this call
+    if (qs_dev && hipMemcpy(qs_dev, s.data(), n * 4, hipMemcpyHostToDevice) != hipSuccess) return WQ_EDEVICE;
+    if (qc_dev && hipMemcpy(qc_dev, c.data(), n * 4, hipMemcpyHostToDevice) != hipSuccess) return WQ_EDEVICE;
+  }
+  return WQ_OK;
+}
+
+wq_status wq_field(const wq_plan* plan, void* field_dev, hipStream_t stream) {
+  if (!plan || !field_dev) return WQ_EINVAL;
+  if (!plan->setup_done) return WQ_ESTATE;
+  const size_t bytes = size_t(wq::kNumChannels) * size_t(plan->nqtot) * (plan->prec == WQ_FP64 ? 8 : 4);
+  hipError_t e = hipMemcpyAsync(field_dev, plan->ws + plan->lay.field, bytes, hipMemcpyDeviceToDevice, stream);
+  return e == hipSuccess ? WQ_OK : WQ_EDEVICE;
+}
+
+wq_status wq_sync(wq_plan* plan, hipStream_t stream) {
+  if (!plan) return WQ_EINVAL;
+  hipError_t e = hipStreamSynchronize(stream);
+  if (e != hipSuccess) return hip_fail(plan, e, "wq_sync");
+  if (!plan->bound) return WQ_OK;
+  int32_t f[wq::kNumFlags];
+  e = hipMemcpy(f, plan->ws + plan->lay.flags, sizeof(f), hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return hip_fail(plan, e, "wq_sync: flag read");
+  wq_status st = WQ_OK;
+  char buf[256];
+  if (f[wq::FLAG_SOLVE_BAD] > 0) {
+    std::snprintf(buf, sizeof buf, "%d weight systems broke down (first: %d)", f[wq::FLAG_SOLVE_BAD], f[wq::FLAG_SOLVE_FIRST]);
+    plan->err = buf;
+    st = WQ_ESINGULAR;
+  }
+  if (f[wq::FLAG_DETJ_BAD] > 0) {
+    std::snprintf(buf, sizeof buf, "det J <= 0 at %d quadrature points (first linear index %d)", f[wq::FLAG_DETJ_BAD], f[wq::FLAG_DETJ_FIRST]);
+    plan->err = buf;
+    st = WQ_EGEOM;
+  }
+  if (st != WQ_OK) {
+    const int32_t zero[4] = {0, 0x7fffffff, 0, 0x7fffffff};
+    e = hipMemcpy(plan->ws + plan->lay.flags, zero, sizeof(zero), hipMemcpyHostToDevice);
+    if (e != hipSuccess) return hip_fail(plan, e, "wq_sync: flag clear");
+  }
+  return st;
+}
+
+const char* wq_last_error(const wq_plan* plan) { return plan ? plan->err.c_str() : "null plan"; }
+
+void wq_plan_destroy(wq_plan* plan) { delete plan; }
+
+}  // extern "C"

@@ -1,0 +1,639 @@
+// Setup kernels: quadrature points and B-spline tables (Algorithm 1), the
+// univariate weighted-quadrature rules (Algorithm 2), the geometry/coefficient
+// field (Section 3, eqs. mass2 and coef_stiff), and the CSR pattern
+// (Section 3, sets I_i).
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+
+#include "wq_dd.h"
+#include "wq_internal.h"
+
+namespace wq {
+namespace {
+
+// Values N[r] and first derivatives D[r] at x of the degree-P B-splines
+// s-P+r, r = 0..P, nonzero on the knot span [U[s], U[s+1]) (Cox-de Boor
+// triangular recursion; derivatives from the degree P-1 values).  R is
+// double or dd.
+// Knot difference a - b: exact in double-double, rounded in FP64.
+template <typename R> __device__ inline R knot_diff(double a, double b);
+template <> __device__ inline double knot_diff<double>(double a, double b) { return a - b; }
+template <> __device__ inline dd knot_diff<dd>(double a, double b) { return two_sum(a, -b); }
+
+template <int P, typename R>
+__device__ inline void basis_funs(const double* __restrict__ U, int s, R x, R (&N)[P + 1], R (&D)[P + 1]) {
+  R left[P + 1], right[P + 1], Nm[P + 1];
+  N[0] = R{1.0};
+#pragma unroll
+  for (int j = 1; j <= P; ++j) {
+    left[j] = x - U[s + 1 - j];
+    right[j] = U[s + j] - x;
+    if (j == P) {
+#pragma unroll
+      for (int r = 0; r < P; ++r) Nm[r] = N[r];
+    }
+    R saved{0.0};
+#pragma unroll
+    for (int r = 0; r < j; ++r) {
+      const R temp = N[r] / (right[r + 1] + left[j - r]);
+      N[r] = saved + right[r + 1] * temp;
+      saved = left[j - r] * temp;
+    }
+    N[j] = saved;
+  }
+#pragma unroll
+  for (int r = 0; r <= P; ++r) {
+    const int i = s - P + r;
+    R d{0.0};
+    if (r >= 1) d = d + (Nm[r - 1] * double(P)) / knot_diff<R>(U[i + P], U[i]);
+    if (r <= P - 1) d = d - (Nm[r] * double(P)) / knot_diff<R>(U[i + P + 1], U[i + 1]);
+    D[r] = d;
+  }
+}
+
+// Quadrature point q of a direction (layout of Remark 4.1, see
+// wq_internal.h) in double-double, and the span e holding it (interior
+// knots are assigned to the span on their right).
+__device__ inline dd qp_coord(const double* __restrict__ k, int P, int nel, int q, int& e) {
+  if (q <= P) {
+    e = 0;
+    const dd h = two_sum(k[P + 1], -k[P]);
+    return (h * double(q + 1)) / double(P + 2) + k[P];
+  }
+  if (q >= P + 2 * nel - 2) {
+    e = nel - 1;
+    const int t = q - (P + 2 * nel - 2);
+    const dd h = two_sum(k[P + nel], -k[P + nel - 1]);
+    return (h * double(t + 1)) / double(P + 2) + k[P + nel - 1];
+  }
+  const int m = q - P;
+  if (m & 1) {
+    e = (m + 1) / 2;
+    return dd_from(k[P + e]);
+  }
+  e = m / 2;
+  const dd s = two_sum(k[P + e], k[P + e + 1]);
+  return dd{0.5 * s.hi, 0.5 * s.lo};
+}
+
+__device__ inline double wave_sum(double x) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) x += __shfl_xor(x, off, 64);
+  return x;
+}
+
+// ---------------------------------------------------------------------------
+// Quadrature points and the p+1 nonzero B-spline values/derivatives there
+// (FP64 tables for the geometry stage).
+template <int P>
+__global__ __launch_bounds__(256) void k_points(PlanView v) {
+  const int dir = blockIdx.y;
+  const DirView d = v.dir[dir];
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= d.nq) return;
+  int e;
+  const dd xd = qp_coord(d.knots, P, d.nel, q, e);
+  const double x = xd.hi;
+  double N[P + 1], D[P + 1], Nm[P], Dm[P];
+  basis_funs<P, double>(d.knots, e + P, x, N, D);
+  basis_funs<P - 1, double>(d.knots, e + P, x, Nm, Dm);   // degree p-1, functions e+1 .. e+p
+  d.x[q] = x;
+  d.qspan[q] = e;
+#pragma unroll
+  for (int r = 0; r <= P; ++r) {
+    d.bv[q * (P + 1) + r] = N[r];
+    d.bd[q * (P + 1) + r] = D[r];
+  }
+  // derivative of a spline: sum_i C_i B_i' = sum_i (C_i - C_{i-1}) P N_{i,P-1} / (xi_{i+P} - xi_i)
+#pragma unroll
+  for (int r = 0; r < P; ++r) {
+    const int i = e + 1 + r;
+    d.bw[q * P + r] = P * Nm[r] / (d.knots[i + P] - d.knots[i]);
+  }
+}
+
+// Differenced control net along each direction b: C_i - C_{i - e_b} (exact
+// inputs, so each difference is correctly rounded); zero where i_b = 0.
+__global__ __launch_bounds__(256) void k_ctrl_diff(PlanView v) {
+  const int n1 = v.dir[0].n, n2 = v.dir[1].n, n3 = v.dir[2].n;
+  const int64_t N = int64_t(n1) * n2 * n3;
+  const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (t >= N * 3) return;
+  const int64_t i = t / 3;
+  const int a = int(t % 3);
+  const int i1 = int(i % n1), i2 = int((i / n1) % n2), i3 = int(i / (int64_t(n1) * n2));
+  const double c = v.ctrl[t];
+  v.dctrl[0 * N * 3 + t] = i1 > 0 ? c - v.ctrl[(i - 1) * 3 + a] : 0.0;
+  v.dctrl[1 * N * 3 + t] = i2 > 0 ? c - v.ctrl[(i - n1) * 3 + a] : 0.0;
+  v.dctrl[2 * N * 3 + t] = i3 > 0 ? c - v.ctrl[(i - int64_t(n1) * n2) * 3 + a] : 0.0;
+}
+
+// ---------------------------------------------------------------------------
+// Univariate rules: one workgroup (4 wavefronts) per (direction, test index i).
+// Wavefront w handles pairing w = 2*beta + alpha: the minimum-norm w with
+//   sum_q w_q B_j^(alpha)(x_q) = int B_i^(beta) B_j^(alpha),  j in I_i, q in Q_i
+// (Algorithm 2).  For alpha = 1 the last equation is dropped: the equations
+// sum to zero because the B-splines overlapping B_i sum to one on its
+// support, and the remaining ones have full rank.
+//
+// Precision: the systems are ill-conditioned (condition numbers up to ~1e8
+// at p = 6), so their data -- points, B-spline values, Gauss nodes/weights
+// and integrals -- are formed in double-double.  The minimum-norm problem is
+// the KKT system  w - A^T lam = 0,  A w = b;  it is solved with a Householder
+// QR of A^T (lane = quadrature point = row of A^T) in FP64 and refined twice
+// with residuals evaluated in double-double, which yields the weights to
+// FP64 rounding.
+template <int P>
+__global__ __launch_bounds__(256) void k_rules(PlanView v) {
+  constexpr int QC = 3 * P + 1, IC = 2 * P + 1, NG = P + 1, MAXG = (P + 1) * NG;
+  static_assert(QC <= 64, "one wavefront per system");
+  const int dir = blockIdx.y;
+  const DirView d = v.dir[dir];
+  const int i = blockIdx.x;
+  if (i >= d.n) return;   // uniform per block
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int n = d.n, nel = d.nel;
+  int qs, qc, is, ic;
+  q_range(i, P, nel, qs, qc);
+  i_range(i, P, n, is, ic);
+
+  __shared__ dd gx[NG], gw[NG];
+  __shared__ dd gval[MAXG][P + 1], gder[MAXG][P + 1], gwt[MAXG];
+  __shared__ int gspan[MAXG];
+  __shared__ dd A[2][IC][QC];
+  __shared__ dd bvec[4][IC];
+  __shared__ double Rl[4][IC][IC];
+
+  // Gauss-Legendre nodes/weights on [-1, 1]: Newton's method on the
+  // Legendre polynomial P_NG, in FP64 to convergence, then in double-double.
+  if (tid < NG) {
+    double z = cos(M_PI * (tid + 0.75) / (NG + 0.5));
+    for (int it = 0; it < 100; ++it) {
+      double p0 = 1.0, p1 = z;
+      for (int k = 2; k <= NG; ++k) {
+        const double p2 = ((2 * k - 1) * z * p1 - (k - 1) * p0) / k;
+        p0 = p1;
+        p1 = p2;
+      }
+      const double dz = p1 / (NG * (z * p1 - p0) / (z * z - 1.0));
+      z -= dz;
+      if (fabs(dz) <= 1e-15) break;
+    }
+    dd zz = dd_from(z), dp{0.0, 0.0};
+    for (int it = 0; it < 3; ++it) {
+      dd p0 = dd_from(1.0), p1 = zz;
+      for (int k = 2; k <= NG; ++k) {
+        const dd p2 = ((zz * p1) * double(2 * k - 1) - p0 * double(k - 1)) / double(k);
+        p0 = p1;
+        p1 = p2;
+      }
+      dp = ((zz * p1 - p0) * double(NG)) / (zz * zz - 1.0);
+      if (it < 2) zz = zz - p1 / dp;
+    }
+    gx[tid] = zz;
+    gw[tid] = 2.0 / ((1.0 - zz * zz) * (dp * dp));
+  }
+  // A^(alpha)[jj][qq] = B^(alpha)_{is+jj}(x_{qs+qq}) in double-double.
+  for (int idx = tid; idx < 2 * IC * QC; idx += 256) (&A[0][0][0])[idx] = dd{0.0, 0.0};
+  __syncthreads();
+  for (int qq = tid; qq < qc; qq += 256) {
+    int e;
+    const dd x = qp_coord(d.knots, P, nel, qs + qq, e);
+    dd N[P + 1], D[P + 1];
+    basis_funs<P, dd>(d.knots, e + P, x, N, D);
+#pragma unroll
+    for (int r = 0; r <= P; ++r) {
+      const int jj = e + r - is;
+      if (jj >= 0 && jj < ic) {
+        A[0][jj][qq] = N[r];
+        A[1][jj][qq] = D[r];
+      }
+    }
+  }
+  __syncthreads();
+  // B-splines at the Gauss points of the knot-spans supporting B_i.
+  const int e0 = i - P > 0 ? i - P : 0;
+  const int e1 = i + 1 < nel ? i + 1 : nel;
+  const int ng = (e1 - e0) * NG;
+  for (int g = tid; g < ng; g += 256) {
+    const int e = e0 + g / NG, t = g % NG;
+    const double a = d.knots[e + P], b = d.knots[e + P + 1];
+    const dd half = two_sum(b, -a) * 0.5;
+    const dd xg = two_sum(a, b) * 0.5 + half * gx[t];
+    dd N[P + 1], D[P + 1];
+    basis_funs<P, dd>(d.knots, e + P, xg, N, D);
+#pragma unroll
+    for (int r = 0; r <= P; ++r) {
+      gval[g][r] = N[r];
+      gder[g][r] = D[r];
+    }
+    gwt[g] = half * gw[t];
+    gspan[g] = e;
+  }
+  __syncthreads();
+  // Exact 1D integrals (degree <= 2p per span, p+1 Gauss points), in dd.
+  for (int idx = tid; idx < 4 * IC; idx += 256) {
+    const int pair = idx / IC, jj = idx % IC, al = pair & 1, be = pair >> 1;
+    dd s{0.0, 0.0};
+    if (jj < ic) {
+      const int j = is + jj;
+      for (int g = 0; g < ng; ++g) {
+        const int ri = i - gspan[g], rj = j - gspan[g];
+        if (ri >= 0 && ri <= P && rj >= 0 && rj <= P)
+          s += gwt[g] * (be ? gder[g][ri] : gval[g][ri]) * (al ? gder[g][rj] : gval[g][rj]);
+      }
+    }
+    bvec[pair][jj] = s;
+  }
+  __syncthreads();
+
+  // ---- minimum-norm solve, one wavefront per pairing ----
+  const int pair = wave, al = pair & 1;
+  const int r = ic - al;
+  const bool live = lane < qc;
+  double m[IC], vk[IC], vn[IC];
+#pragma unroll
+  for (int j = 0; j < IC; ++j) {
+    m[j] = (live && j < r) ? A[al][j][lane].hi : 0.0;
+    vk[j] = 0.0;
+    vn[j] = 1.0;
+  }
+  bool broke = false;
+#pragma unroll
+  for (int k = 0; k < IC; ++k) {
+    if (k < r) {
+      const double xk = (lane >= k) ? m[k] : 0.0;
+      const double nrm2 = wave_sum(xk * xk);
+      const double akk = __shfl(m[k], k, 64);
+      if (nrm2 > 0.0) {
+        const double nrm = sqrt(nrm2);
+        const double alpha = akk >= 0.0 ? -nrm : nrm;
+        const double vv = (lane == k) ? akk - alpha : xk;
+        const double vnorm2 = 2.0 * (nrm2 + fabs(akk) * nrm);
+        vk[k] = vv;
+        vn[k] = vnorm2;
+#pragma unroll
+        for (int j = 0; j < IC; ++j) {
+          if (j >= k && j < r) {
+            const double s = wave_sum(vv * m[j]);
+            m[j] -= (2.0 * s / vnorm2) * vv;
+          }
+        }
+      } else {
+        broke = true;
+      }
+    }
+  }
+  if (lane < r) {
+#pragma unroll
+    for (int j = 0; j < IC; ++j) Rl[pair][lane][j] = m[j];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < IC; ++k)
+    if (k < r && Rl[pair][k][k] == 0.0) broke = true;
+
+  // KKT iterations from (w, lam) = 0; the first one is the plain solve.
+  dd w{0.0, 0.0};
+  dd lam[IC];
+#pragma unroll
+  for (int j = 0; j < IC; ++j) lam[j] = dd{0.0, 0.0};
+  for (int it = 0; it < 3 && !broke; ++it) {
+    // r2 = b - A w (kept equations), r1 = A^T lam - w (this lane)
+    double r2[IC];
+    dd r1 = -w;
+#pragma unroll
+    for (int j = 0; j < IC; ++j) {
+      r2[j] = 0.0;
+      if (j < r) {
+        const dd a = live ? A[al][j][lane] : dd{0.0, 0.0};
+        const dd s = dd_wave_sum(a * w);
+        r2[j] = dd_to_double(bvec[pair][j] - s);
+        r1 += a * lam[j];
+      }
+    }
+    // t = (Q^T r1)[0:r]: apply H_0 .. H_{r-1}
+    double u = live ? dd_to_double(r1) : 0.0;
+#pragma unroll
+    for (int k = 0; k < IC; ++k)
+      if (k < r) u -= (2.0 * wave_sum(vk[k] * u) / vn[k]) * vk[k];
+    // z = R^{-T} r2 (forward substitution); s = z - t
+    double z[IC], sv[IC];
+#pragma unroll
+    for (int k = 0; k < IC; ++k) {
+      z[k] = 0.0;
+      sv[k] = 0.0;
+      if (k < r) {
+        double acc = r2[k];
+#pragma unroll
+        for (int mm = 0; mm < k; ++mm) acc -= Rl[pair][mm][k] * z[mm];
+        z[k] = acc / Rl[pair][k][k];
+        sv[k] = z[k] - __shfl(u, k, 64);
+      }
+    }
+    // dlam = R^{-1} s (back substitution)
+    double dl[IC];
+#pragma unroll
+    for (int k = IC - 1; k >= 0; --k) {
+      dl[k] = 0.0;
+      if (k < r) {
+        double z = sv[k];
+#pragma unroll
+        for (int mm = k + 1; mm < IC; ++mm)
+          if (mm < r) z -= Rl[pair][k][mm] * dl[mm];
+        dl[k] = z / Rl[pair][k][k];
+      }
+    }
+    // dw = r1 + Q [s; 0]: apply H_{r-1} .. H_0
+    double g = 0.0;
+#pragma unroll
+    for (int k = 0; k < IC; ++k)
+      if (lane == k && k < r) g = sv[k];
+#pragma unroll
+    for (int k = IC - 1; k >= 0; --k)
+      if (k < r) g -= (2.0 * wave_sum(vk[k] * g) / vn[k]) * vk[k];
+    if (live) w = (w + r1) + g;
+#pragma unroll
+    for (int j = 0; j < IC; ++j)
+      if (j < r) lam[j] = lam[j] + dl[j];
+  }
+  const double wq = live ? dd_to_double(w) : 0.0;
+  // residual of all ic equations (including a dropped one), in dd
+  double bmax = 0.0, rmax = 0.0;
+  for (int j = 0; j < ic; ++j) {
+    const dd a = live ? A[al][j][lane] : dd{0.0, 0.0};
+    const dd s = dd_wave_sum(a * wq);
+    bmax = fmax(bmax, fabs(bvec[pair][j].hi));
+    rmax = fmax(rmax, fabs(dd_to_double(s - bvec[pair][j])));
+  }
+  if (!(rmax <= 1e-9 * bmax + 1e-300) || broke) {
+    if (lane == 0) {
+      atomicAdd(&v.flags[FLAG_SOLVE_BAD], 1);
+      atomicMin(&v.flags[FLAG_SOLVE_FIRST], (dir * 4 + pair) * n + i);
+    }
+  }
+  // outputs
+  if (lane < QC) {
+    d.w[(size_t(pair) * n + i) * QC + lane] = wq;
+#pragma unroll
+    for (int jj = 0; jj < IC; ++jj) {
+      const double b = dd_to_double(A[al][jj][lane]);
+      const double t = b * wq;
+      const size_t o = ((size_t(pair) * n + i) * IC + jj) * QC + lane;
+      d.op64[o] = t;
+      d.op32[o] = float(t);
+      if (pair < 2) {   // the B^(alpha) tables, alpha = pair
+        d.bt64[o] = b;
+        d.bt32[o] = float(b);
+      }
+    }
+  }
+}
+
+// Prefix sums of the 1D row lengths #I_i (one thread per direction).
+__global__ void k_prefix(PlanView v) {
+  const int dir = threadIdx.x;
+  if (dir >= 3) return;
+  const DirView d = v.dir[dir];
+  int64_t s = 0;
+  d.prefix[0] = 0;
+  for (int i = 0; i < d.n; ++i) {
+    int is, ic;
+    i_range(i, v.p, d.n, is, ic);
+    s += ic;
+    d.prefix[i + 1] = s;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Geometry at every quadrature point: F = sum_i C_i B_i and the Jacobian
+// J = dF/dzeta, whose column b is evaluated from the control net differenced
+// along b and the non-negative weights P N_{i,P-1} / (xi_{i+P} - xi_i) (no
+// cancellation, unlike sum_i C_i dB_i/dzeta_b); then det J and the
+// coefficient field (det J; K = a det J J^{-1} J^{-T}).
+template <int P, typename T, bool XPHYS>
+__global__ __launch_bounds__(256) void k_geometry(PlanView v, const double* __restrict__ coef,
+                                                  double* __restrict__ xphys) {
+  const int64_t q = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (q >= v.nqtot) return;
+  const DirView d1 = v.dir[0], d2 = v.dir[1], d3 = v.dir[2];
+  const int q1 = int(q % d1.nq);
+  const int q2 = int((q / d1.nq) % d2.nq);
+  const int q3 = int(q / (int64_t(d1.nq) * d2.nq));
+  const int e1 = d1.qspan[q1], e2 = d2.qspan[q2], e3 = d3.qspan[q3];
+  // direction-1 tables in registers; weight of the difference C_{e+r} - C_{e+r-1}
+  // is w[r] (none for r = 0)
+  double v1[P + 1], w1[P + 1];
+#pragma unroll
+  for (int r = 0; r <= P; ++r) {
+    v1[r] = d1.bv[q1 * (P + 1) + r];
+    w1[r] = r ? d1.bw[q1 * P + r - 1] : 0.0;
+  }
+  const double* bv2 = d2.bv + q2 * (P + 1);
+  const double* bv3 = d3.bv + q3 * (P + 1);
+  const double* bw2 = d2.bw + q2 * P - 1;   // bw2[r] for r >= 1
+  const double* bw3 = d3.bw + q3 * P - 1;
+  const int n1 = d1.n, n2 = d2.n;
+  const size_t NC = size_t(n1) * n2 * d3.n * 3;
+  if (XPHYS) {
+    double F[3] = {0, 0, 0};
+#pragma unroll 1
+    for (int l3 = 0; l3 <= P; ++l3) {
+      double f2[3] = {0, 0, 0};
+#pragma unroll 1
+      for (int l2 = 0; l2 <= P; ++l2) {
+        const double* c = v.ctrl + ((size_t(e3 + l3) * n2 + (e2 + l2)) * n1 + e1) * 3;
+        double f1[3] = {0, 0, 0};
+#pragma unroll
+        for (int l1 = 0; l1 <= P; ++l1)
+#pragma unroll
+          for (int a = 0; a < 3; ++a) f1[a] += c[l1 * 3 + a] * v1[l1];
+        const double b2 = bv2[l2];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) f2[a] += f1[a] * b2;
+      }
+      const double b3 = bv3[l3];
+#pragma unroll
+      for (int a = 0; a < 3; ++a) F[a] += f2[a] * b3;
+    }
+#pragma unroll
+    for (int a = 0; a < 3; ++a) xphys[q * 3 + a] = F[a];
+    return;
+  }
+  const double* C1 = v.dctrl;
+  const double* C2 = v.dctrl + NC;
+  const double* C3 = v.dctrl + 2 * NC;
+  double J[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+#pragma unroll 1
+  for (int l3 = 0; l3 <= P; ++l3) {
+    double j02[3] = {0, 0, 0}, j12[3] = {0, 0, 0}, j22[3] = {0, 0, 0};
+#pragma unroll 1
+    for (int l2 = 0; l2 <= P; ++l2) {
+      const size_t o = ((size_t(e3 + l3) * n2 + (e2 + l2)) * n1 + e1) * 3;
+      double j01[3] = {0, 0, 0}, j11[3] = {0, 0, 0}, j21[3] = {0, 0, 0};
+#pragma unroll
+      for (int l1 = 0; l1 <= P; ++l1) {
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+          const size_t k = o + l1 * 3 + a;
+          if (l1) j01[a] += C1[k] * w1[l1];
+          j11[a] += C2[k] * v1[l1];
+          j21[a] += C3[k] * v1[l1];
+        }
+      }
+      const double b2 = bv2[l2];
+      const double g2 = l2 ? bw2[l2] : 0.0;
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        j02[a] += j01[a] * b2;
+        j12[a] += j11[a] * g2;
+        j22[a] += j21[a] * b2;
+      }
+    }
+    const double b3 = bv3[l3];
+    const double g3 = l3 ? bw3[l3] : 0.0;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      J[a][0] += j02[a] * b3;
+      J[a][1] += j12[a] * b3;
+      J[a][2] += j22[a] * g3;
+    }
+  }
+  // cofactors C_ab; adj(J) = C^T; det J = sum_b J_0b C_0b
+  const double c00 = J[1][1] * J[2][2] - J[1][2] * J[2][1];
+  const double c01 = J[1][2] * J[2][0] - J[1][0] * J[2][2];
+  const double c02 = J[1][0] * J[2][1] - J[1][1] * J[2][0];
+  const double c10 = J[0][2] * J[2][1] - J[0][1] * J[2][2];
+  const double c11 = J[0][0] * J[2][2] - J[0][2] * J[2][0];
+  const double c12 = J[0][1] * J[2][0] - J[0][0] * J[2][1];
+  const double c20 = J[0][1] * J[1][2] - J[0][2] * J[1][1];
+  const double c21 = J[0][2] * J[1][0] - J[0][0] * J[1][2];
+  const double c22 = J[0][0] * J[1][1] - J[0][1] * J[1][0];
+  const double det = J[0][0] * c00 + J[0][1] * c01 + J[0][2] * c02;
+  if (!(det > 0.0) || !isfinite(det)) {
+    atomicAdd(&v.flags[FLAG_DETJ_BAD], 1);
+    atomicMin(&v.flags[FLAG_DETJ_FIRST], int(q));
+  }
+  // K_lm = a * sum_k adj(J)_lk adj(J)_mk / det = a * sum_k C_kl C_km / det
+  const double s = (coef ? coef[q] : 1.0) / det;
+  const double K11 = s * (c00 * c00 + c10 * c10 + c20 * c20);
+  const double K22 = s * (c01 * c01 + c11 * c11 + c21 * c21);
+  const double K33 = s * (c02 * c02 + c12 * c12 + c22 * c22);
+  const double K12 = s * (c00 * c01 + c10 * c11 + c20 * c21);
+  const double K13 = s * (c00 * c02 + c10 * c12 + c20 * c22);
+  const double K23 = s * (c01 * c02 + c11 * c12 + c21 * c22);
+  T* f = static_cast<T*>(v.field);
+  const int64_t N = v.nqtot;
+  f[0 * N + q] = T(det);
+  f[1 * N + q] = T(K11);
+  f[2 * N + q] = T(K22);
+  f[3 * N + q] = T(K33);
+  f[4 * N + q] = T(K12);
+  f[5 * N + q] = T(K13);
+  f[6 * N + q] = T(K23);
+}
+
+// ---------------------------------------------------------------------------
+// CSR pattern: one wavefront per row.
+__global__ __launch_bounds__(256) void k_pattern(PlanView v, int64_t* __restrict__ row_ptr,
+                                                 int32_t* __restrict__ col_idx) {
+  const int lane = threadIdx.x & 63;
+  const int64_t row = int64_t(blockIdx.x) * 4 + (threadIdx.x >> 6);
+  const DirView d1 = v.dir[0], d2 = v.dir[1], d3 = v.dir[2];
+  const int n1 = d1.n, n2 = d2.n, n3 = d3.n;
+  const int64_t nrows = int64_t(n1) * n2 * n3;
+  if (row >= nrows) return;
+  const int i1 = int(row % n1), i2 = int((row / n1) % n2), i3 = int(row / (int64_t(n1) * n2));
+  int is1, ic1, is2, ic2, is3, ic3;
+  i_range(i1, v.p, n1, is1, ic1);
+  i_range(i2, v.p, n2, is2, ic2);
+  i_range(i3, v.p, n3, is3, ic3);
+  const int64_t T1 = d1.prefix[n1], T2 = d2.prefix[n2];
+  const int64_t start = d3.prefix[i3] * T2 * T1 + int64_t(ic3) * (d2.prefix[i2] * T1 + int64_t(ic2) * d1.prefix[i1]);
+  const int len = ic1 * ic2 * ic3;
+  if (lane == 0) {
+    row_ptr[row] = start;
+    if (row == nrows - 1) row_ptr[nrows] = start + len;
+  }
+  for (int t = lane; t < len; t += 64) {
+    const int jj1 = t % ic1, tt = t / ic1, jj2 = tt % ic2, jj3 = tt / ic2;
+    col_idx[start + t] = (is1 + jj1) + n1 * ((is2 + jj2) + n2 * (is3 + jj3));
+  }
+}
+
+template <int P>
+hipError_t points_p(const PlanView& v, hipStream_t s) {
+  int maxq = 0;
+  for (int k = 0; k < 3; ++k) maxq = v.dir[k].nq > maxq ? v.dir[k].nq : maxq;
+  dim3 grid((maxq + 255) / 256, 3);
+  hipLaunchKernelGGL(k_points<P>, grid, dim3(256), 0, s, v);
+  return hipGetLastError();
+}
+
+template <int P>
+hipError_t rules_p(const PlanView& v, hipStream_t s) {
+  int maxn = 0;
+  for (int k = 0; k < 3; ++k) maxn = v.dir[k].n > maxn ? v.dir[k].n : maxn;
+  hipLaunchKernelGGL(k_rules<P>, dim3(maxn, 3), dim3(256), 0, s, v);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_prefix, dim3(1), dim3(64), 0, s, v);
+  return hipGetLastError();
+}
+
+template <int P>
+hipError_t geometry_p(const PlanView& v, const double* coef, double* xphys, hipStream_t s) {
+  const unsigned blocks = unsigned((v.nqtot + 255) / 256);
+  if (xphys)
+    hipLaunchKernelGGL((k_geometry<P, double, true>), dim3(blocks), dim3(256), 0, s, v, coef, xphys);
+  else if (v.prec == WQ_FP64)
+    hipLaunchKernelGGL((k_geometry<P, double, false>), dim3(blocks), dim3(256), 0, s, v, coef, xphys);
+  else
+    hipLaunchKernelGGL((k_geometry<P, float, false>), dim3(blocks), dim3(256), 0, s, v, coef, xphys);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+#define WQ_DISPATCH_P(p, CALL) \
+  switch (p) {                 \
+    case 2: return CALL(2);    \
+    case 3: return CALL(3);    \
+    case 4: return CALL(4);    \
+    case 5: return CALL(5);    \
+    case 6: return CALL(6);    \
+    default: return hipErrorInvalidValue; \
+  }
+
+hipError_t launch_points(const PlanView& v, hipStream_t s) {
+#define C(P) points_p<P>(v, s)
+  WQ_DISPATCH_P(v.p, C)
+#undef C
+}
+
+hipError_t launch_rules(const PlanView& v, hipStream_t s) {
+#define C(P) rules_p<P>(v, s)
+  WQ_DISPATCH_P(v.p, C)
+#undef C
+}
+
+hipError_t launch_geometry(const PlanView& v, const double* coef, double* xphys, hipStream_t s) {
+#define C(P) geometry_p<P>(v, coef, xphys, s)
+  WQ_DISPATCH_P(v.p, C)
+#undef C
+}
+
+hipError_t launch_ctrl_diff(const PlanView& v, hipStream_t s) {
+  const int64_t N = int64_t(v.dir[0].n) * v.dir[1].n * v.dir[2].n * 3;
+  hipLaunchKernelGGL(k_ctrl_diff, dim3(unsigned((N + 255) / 256)), dim3(256), 0, s, v);
+  return hipGetLastError();
+}
+
+hipError_t launch_pattern(const PlanView& v, int64_t* row_ptr, int32_t* col_idx, hipStream_t s) {
+  const int64_t nrows = int64_t(v.dir[0].n) * v.dir[1].n * v.dir[2].n;
+  hipLaunchKernelGGL(k_pattern, dim3(unsigned((nrows + 3) / 4)), dim3(256), 0, s, v, row_ptr, col_idx);
+  return hipGetLastError();
+}
+
+}  // namespace wq

@@ -1,0 +1,114 @@
+"""C-ABI tests that need no GPU: the library loads, exports every symbol
+declared in include/wq.h, and its host-only calls validate inputs and
+compute sizes and quadrature points (no compute calls)."""
+import ctypes as C
+import os
+import re
+from fractions import Fraction as Fr
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+LIB = os.path.join(ROOT, "paper_1605_01238_amd", "libwq.so")
+
+pytestmark = pytest.mark.skipif(not os.path.exists(LIB), reason="libwq.so not built")
+
+
+def declared_symbols():
+    txt = open(os.path.join(ROOT, "include", "wq.h")).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(wq_[a-z_]+)\s*\(", txt)))
+
+
+def test_exports_every_declared_symbol():
+    from paper_1605_01238_amd import _wq
+    names = declared_symbols()
+    assert len(names) >= 15
+    lib = C.CDLL(LIB)
+    for n in names:
+        assert hasattr(lib, n), n
+    assert set(names) == {s[0] for s in _wq.SIGNATURES}
+    assert _wq.wq_version().startswith(b"wq-gfx950")
+
+
+def make(knots3, p, prec=0):
+    from paper_1605_01238_amd import _wq
+    ks = [np.ascontiguousarray(k, dtype=np.float64) for k in knots3]
+    n_knots = (C.c_int64 * 3)(*[len(k) for k in ks])
+    ptrs = (C.POINTER(C.c_double) * 3)(*[k.ctypes.data_as(C.POINTER(C.c_double)) for k in ks])
+    h = C.c_void_p()
+    st = _wq.wq_plan_create(3, p, n_knots, ptrs, prec, C.byref(h))
+    return st, h
+
+
+@pytest.mark.parametrize("p,nel", [(2, (8, 8, 8)), (4, (32, 32, 32)), (6, (64, 64, 64)), (3, (5, 7, 9))])
+def test_sizes(p, nel):
+    from paper_1605_01238_amd import _wq
+    from workloads import Workload, open_uniform_knots
+    st, h = make([open_uniform_knots(p, e) for e in nel], p)
+    assert st == 0
+    s = _wq.wq_sizes_t()
+    assert _wq.wq_sizes(h, C.byref(s)) == 0
+    w = Workload("t", p, nel, None, None)
+    assert s.nnz == w.exact_nnz()
+    assert tuple(s.n) == w.n_dof()
+    assert tuple(s.n_qp) == tuple(2 * e + 2 * p - 1 for e in nel)
+    assert s.value_bytes == 8 * s.nnz and s.workspace_bytes > 0
+    _wq.wq_plan_destroy(h)
+
+
+@pytest.mark.parametrize("p,nel,uniform", [(2, 8, True), (5, 9, False), (6, 11, True)])
+def test_host_quadrature_points_match_oracle(p, nel, uniform):
+    from oracle.rules import quadrature_points
+    from oracle.splines import exact_knots
+    from paper_1605_01238_amd import _wq
+    from workloads import open_uniform_knots, random_open_knots
+    k = open_uniform_knots(p, nel) if uniform else random_open_knots(p, nel, seed=7)
+    st, h = make([k, k, k], p)
+    assert st == 0
+    x = np.zeros(2 * nel + 2 * p - 1)
+    assert _wq.wq_qpoints(h, 1, x.ctypes.data_as(C.POINTER(C.c_double))) == 0
+    ref = np.array([float(v) for v in quadrature_points(exact_knots(list(k)), p)])
+    assert np.abs(x - ref).max() <= 4e-16
+    _wq.wq_plan_destroy(h)
+
+
+def test_invalid_inputs_rejected():
+    from paper_1605_01238_amd import _wq
+    from workloads import open_uniform_knots
+    good = open_uniform_knots(3, 6)
+    assert make([good] * 3, 1)[0] == _wq.WQ_EINVAL            # p below the minimum
+    assert make([good] * 3, 7)[0] == _wq.WQ_EINVAL            # p above the maximum
+    assert make([good] * 3, 3, prec=5)[0] == _wq.WQ_EINVAL    # precision
+    bad = good.copy(); bad[5], bad[6] = bad[6], bad[5]        # decreasing
+    assert make([good, bad, good], 3)[0] == _wq.WQ_EKNOTS
+    notopen = good.copy(); notopen[0] = -0.1
+    assert make([notopen, good, good], 3)[0] == _wq.WQ_EKNOTS
+    rep = good.copy(); rep[5] = rep[6]                        # repeated interior knot (C^{p-2})
+    assert make([good, good, rep], 3)[0] == _wq.WQ_EKNOTS
+    few = open_uniform_knots(3, 4)                            # fewer than p+2 spans
+    assert make([good, few, good], 3)[0] == _wq.WQ_EKNOTS
+    nan = good.copy(); nan[4] = np.nan
+    assert make([good, good, nan], 3)[0] == _wq.WQ_EKNOTS
+    h = C.c_void_p()
+    assert _wq.wq_plan_create(3, 3, None, None, 0, C.byref(h)) == _wq.WQ_EINVAL
+
+
+def test_state_and_workspace_errors_without_device():
+    from paper_1605_01238_amd import _wq
+    from workloads import open_uniform_knots
+    st, h = make([open_uniform_knots(2, 5)] * 3, 2)
+    assert st == 0
+    dummy = C.c_void_p(256)
+    # assemble/setup/pattern before bind: state errors, no device call
+    assert _wq.wq_assemble(h, _wq.WQ_STIFF, None, dummy, None) == _wq.WQ_ESTATE
+    assert _wq.wq_setup(h, dummy, None, None) == _wq.WQ_ESTATE
+    assert _wq.wq_pattern(h, dummy, dummy, None) == _wq.WQ_ESTATE
+    assert _wq.wq_assemble(h, 4, None, None, None) == _wq.WQ_EINVAL
+    assert _wq.wq_assemble(h, _wq.WQ_MASS, None, None, None) == _wq.WQ_EINVAL
+    # too small / misaligned workspace are rejected before any upload
+    assert _wq.wq_bind(h, dummy, 16, None) == _wq.WQ_ENOSPACE
+    assert _wq.wq_bind(h, C.c_void_p(257), 1 << 40, None) == _wq.WQ_ENOSPACE
+    assert b"256-byte" in _wq.wq_last_error(h)
+    _wq.wq_plan_destroy(h)
