@@ -19,23 +19,24 @@ def hipcc() -> str:
     raise RuntimeError("hipcc not found")
 
 
-def build(verbose: bool = True) -> str:
-    """Compile every source into libwq.so (always recompiles)."""
+def build(verbose: bool = True, out: str = LIB, defines=()) -> str:
+    """Compile every source into libwq.so (always recompiles).  ``defines``
+    are extra -D settings (tuning knobs of the kernels)."""
     srcs = [os.path.join(HERE, "csrc", s) for s in SOURCES]
-    tmp = LIB + ".tmp"
+    tmp = out + ".tmp"
     cmd = [hipcc(), "-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC", "-shared",
            # packed FP32 instructions are kept out of the device code
            "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
            "-Wno-unused-command-line-argument",
-           "-I", os.path.join(ROOT, "include"), "-o", tmp] + srcs
+           "-I", os.path.join(ROOT, "include"), "-o", tmp] + [f"-D{d}" for d in defines] + srcs
     if verbose:
         print(" ".join(cmd), flush=True)
     res = subprocess.run(cmd, capture_output=True, text=True)
     if res.returncode != 0:
         sys.stderr.write(res.stdout + res.stderr)
         raise RuntimeError("hipcc failed")
-    os.replace(tmp, LIB)
-    return LIB
+    os.replace(tmp, out)
+    return out
 
 
 if __name__ == "__main__":

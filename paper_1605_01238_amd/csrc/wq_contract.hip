@@ -34,6 +34,17 @@
 
 #include "wq_internal.h"
 
+// Unroll factors of the quadrature loops of phases A and B/C (trade register
+// pressure against loads in flight).
+#ifndef WQ_UNROLL_A
+#define WQ_UNROLL_A 2
+#endif
+#ifndef WQ_UNROLL_BC
+#define WQ_UNROLL_BC 4
+#endif
+#define WQ_STR(x) #x
+#define WQ_UNROLL(n) _Pragma(WQ_STR(unroll n))
+
 namespace wq {
 namespace {
 
@@ -45,7 +56,7 @@ template <int P, typename T> struct PencilCfg;
 // in phase C; C: q1 columns per chunk; NT: threads per workgroup.
 template <> struct PencilCfg<2, double> { static constexpr int SC = 1, SA = 1, NP1 = 2, C = 16, NT = 256; };
 template <> struct PencilCfg<3, double> { static constexpr int SC = 1, SA = 2, NP1 = 1, C = 12, NT = 256; };
-template <> struct PencilCfg<4, double> { static constexpr int SC = 1, SA = 3, NP1 = 2, C = 8, NT = 384; };
+template <> struct PencilCfg<4, double> { static constexpr int SC = 2, SA = 2, NP1 = 1, C = 8, NT = 384; };
 template <> struct PencilCfg<5, double> { static constexpr int SC = 2, SA = 2, NP1 = 2, C = 8, NT = 384; };
 template <> struct PencilCfg<6, double> { static constexpr int SC = 2, SA = 2, NP1 = 1, C = 8, NT = 256; };
 template <> struct PencilCfg<2, float> { static constexpr int SC = 1, SA = 1, NP1 = 2, C = 16, NT = 256; };
@@ -79,14 +90,19 @@ struct Shape {
 };
 
 template <typename T>
-__device__ inline const T* op_table(const DirView& d) {
+__device__ inline const T* op_t(const DirView& d) {
   if constexpr (sizeof(T) == 8) return reinterpret_cast<const T*>(d.op64);
   else return reinterpret_cast<const T*>(d.op32);
 }
 template <typename T>
-__device__ inline const T* bt_table(const DirView& d) {
+__device__ inline const T* bt_t(const DirView& d) {
   if constexpr (sizeof(T) == 8) return reinterpret_cast<const T*>(d.bt64);
   else return reinterpret_cast<const T*>(d.bt32);
+}
+template <typename T>
+__device__ inline const T* wt_t(const DirView& d) {
+  if constexpr (sizeof(T) == 8) return reinterpret_cast<const T*>(d.wt64);
+  else return reinterpret_cast<const T*>(d.wt32);
 }
 
 template <int P, typename T, bool STIFF>
@@ -116,13 +132,10 @@ __global__ __launch_bounds__((Shape<P, T, STIFF>::NT)) void k_pencil(PlanView v,
 
   const int64_t N = v.nqtot;
   const T* __restrict__ field = static_cast<const T*>(v.field);
-  // pencil-constant tables (uniform addresses)
-  const T* __restrict__ T3 = op_table<T>(d3) + size_t(i3) * IC * QC;              // + o * n3 * IC * QC
-  const size_t T3o = size_t(d3.n) * IC * QC;
-  const double* __restrict__ w2 = d2.w + size_t(i2) * QC;                        // + o * n2 * QC
-  const size_t w2o = size_t(n2) * QC;
-  const T* __restrict__ B2 = bt_table<T>(d2) + size_t(i2) * IC * QC;             // + a * n2 * IC * QC
-  const size_t B2a = size_t(n2) * IC * QC;
+  // pencil-constant tables (uniform addresses -> scalar loads)
+  const T* __restrict__ T3 = op_t<T>(d3) + size_t(i3) * QC * IC * 4;    // [qq3][jj3][o]
+  const T* __restrict__ w2 = wt_t<T>(d2) + size_t(i2) * QC * 4;         // [qq2][o]
+  const T* __restrict__ B2 = bt_t<T>(d2) + size_t(i2) * QC * IC * 2;    // [qq2][jj2][a]
 
   // CSR position of row (i1, i2, i3): closed-form prefix of the row lengths
   const int64_t Tn1 = d1.prefix[n1], Tn2 = d2.prefix[n2];
@@ -154,41 +167,62 @@ __global__ __launch_bounds__((Shape<P, T, STIFF>::NT)) void k_pencil(PlanView v,
             for (int u = 0; u < J3A; ++u) Y[ch][u] = T(0);
           const T* f = field + q1 + int64_t(nq1) * (q2 + int64_t(nq2) * qs3);
           const int64_t fstride = int64_t(nq1) * nq2;
-          for (int qq3 = 0; qq3 < qc3; ++qq3) {
-            if constexpr (STIFF) {
-              const T k11 = f[1 * N], k22 = f[2 * N], k33 = f[3 * N];
-              const T k12 = f[4 * N], k13 = f[5 * N], k23 = f[6 * N];
+          // field values are loaded for KB consecutive q3 before they are used,
+          // so that several loads are in flight per lane
+          constexpr int KB = 4;
+          constexpr int NF = STIFF ? 6 : 1;
+#pragma unroll 1
+          for (int b0 = 0; b0 < QC; b0 += KB) {
+            if (b0 < qc3) {   // uniform
+              T kv[KB][NF];
 #pragma unroll
-              for (int u = 0; u < J3A; ++u) {
-                const int jj3 = j3lo + ua + u;
-                if (jj3 < IC) {   // uniform
-                  const T* t = T3 + jj3 * QC + qq3;
-                  const T t0 = t[R00 * T3o], t1 = t[R10 * T3o], t2 = t[R01 * T3o], t3 = t[R11 * T3o];
-                  Y[0][u] += t0 * k11;
-                  Y[1][u] += t0 * k22;
-                  Y[2][u] += t3 * k33;
-                  Y[3][u] += t0 * k12;
-                  Y[4][u] += t1 * k13;
-                  Y[5][u] += t2 * k13;
-                  Y[6][u] += t1 * k23;
-                  Y[7][u] += t2 * k23;
+              for (int kb = 0; kb < KB; ++kb) {
+                const int qq3 = b0 + kb;
+                if (qq3 < qc3) {
+                  const T* fk = f + qq3 * fstride;
+#pragma unroll
+                  for (int fi = 0; fi < NF; ++fi) kv[kb][fi] = fk[(STIFF ? fi + 1 : 0) * N];
+                } else {
+#pragma unroll
+                  for (int fi = 0; fi < NF; ++fi) kv[kb][fi] = T(0);
                 }
               }
-            } else {
-              const T c0 = f[0];
 #pragma unroll
-              for (int u = 0; u < J3A; ++u) {
-                const int jj3 = j3lo + ua + u;
-                if (jj3 < IC) Y[0][u] += T3[jj3 * QC + qq3] * c0;
+              for (int kb = 0; kb < KB; ++kb) {
+                const int qq3 = b0 + kb;
+                if (qq3 < qc3) {   // uniform
+                  const T* t = T3 + __builtin_amdgcn_readfirstlane((qq3 * IC + j3lo + ua) * 4);
+                  if constexpr (STIFF) {
+                    const T k11 = kv[kb][0], k22 = kv[kb][1], k33 = kv[kb][2];
+                    const T k12 = kv[kb][3], k13 = kv[kb][4], k23 = kv[kb][5];
+#pragma unroll
+                    for (int u = 0; u < J3A; ++u) {
+                      if (j3lo + ua + u < IC) {   // uniform
+                        const T t0 = t[u * 4 + R00], t1 = t[u * 4 + R10], t2 = t[u * 4 + R01], t3 = t[u * 4 + R11];
+                        Y[0][u] += t0 * k11;
+                        Y[1][u] += t0 * k22;
+                        Y[2][u] += t3 * k33;
+                        Y[3][u] += t0 * k12;
+                        Y[4][u] += t1 * k13;
+                        Y[5][u] += t2 * k13;
+                        Y[6][u] += t1 * k23;
+                        Y[7][u] += t2 * k23;
+                      }
+                    }
+                  } else {
+#pragma unroll
+                    for (int u = 0; u < J3A; ++u)
+                      if (j3lo + ua + u < IC) Y[0][u] += t[u * 4 + R00] * kv[kb][0];
+                  }
+                }
               }
             }
-            f += fstride;
           }
           // fold in the dir-2 weights of this q2 (weight merge)
           T* h = hbuf + (size_t(c) * NH * QC + qq2) * J3A;
           if constexpr (STIFF) {
-            const T a0 = T(w2[R00 * w2o + qq2]), a1 = T(w2[R10 * w2o + qq2]);
-            const T a2 = T(w2[R01 * w2o + qq2]), a3 = T(w2[R11 * w2o + qq2]);
+            const T a0 = w2[qq2 * 4 + R00], a1 = w2[qq2 * 4 + R10];
+            const T a2 = w2[qq2 * 4 + R01], a3 = w2[qq2 * 4 + R11];
 #pragma unroll
             for (int u = 0; u < J3A; ++u) {
               h[0 * QC * J3A + u] = a3 * Y[1][u] + a1 * Y[7][u];   // -> G_(0,0) through B2^(1)
@@ -199,7 +233,7 @@ __global__ __launch_bounds__((Shape<P, T, STIFF>::NT)) void k_pencil(PlanView v,
               h[5 * QC * J3A + u] = a2 * Y[3][u] + a0 * Y[5][u];   // -> G_(1,0) through B2^(0)
             }
           } else {
-            const T a0 = T(w2[qq2]);
+            const T a0 = w2[qq2 * 4 + R00];
 #pragma unroll
             for (int u = 0; u < J3A; ++u) h[u] = a0 * Y[0][u];
           }
@@ -224,14 +258,17 @@ __global__ __launch_bounds__((Shape<P, T, STIFF>::NT)) void k_pencil(PlanView v,
 #pragma unroll
           for (int jj2 = 0; jj2 < IC; ++jj2) G[jj2] = T(0);
           const T* hb = hbuf + size_t(c) * NH * QC * J3A + u;
-          for (int qq2 = 0; qq2 < qc2; ++qq2) {
-            const T x0 = hb[(h0 * QC + qq2) * J3A];
-            const T x1 = h1 >= 0 ? hb[(h1 * QC + qq2) * J3A] : T(0);
+WQ_UNROLL(WQ_UNROLL_BC)
+          for (int qq2 = 0; qq2 < QC; ++qq2) {
+            if (qq2 < qc2) {   // uniform
+              const T x0 = hb[(h0 * QC + qq2) * J3A];
+              const T x1 = h1 >= 0 ? hb[(h1 * QC + qq2) * J3A] : T(0);
+              const T* b = B2 + __builtin_amdgcn_readfirstlane(qq2 * IC * 2);
 #pragma unroll
-            for (int jj2 = 0; jj2 < IC; ++jj2) {
-              const T* b = B2 + jj2 * QC + qq2;
-              if constexpr (STIFF) G[jj2] += b[0] * x0 + b[B2a] * x1;
-              else G[jj2] += b[0] * x0;
+              for (int jj2 = 0; jj2 < IC; ++jj2) {
+                if constexpr (STIFF) G[jj2] += b[jj2 * 2] * x0 + b[jj2 * 2 + 1] * x1;
+                else G[jj2] += b[jj2 * 2] * x0;
+              }
             }
           }
           T* r = ring + ((size_t(q1 % W) * NG + g) * IC) * J3C + ua + u;
@@ -244,7 +281,7 @@ __global__ __launch_bounds__((Shape<P, T, STIFF>::NT)) void k_pencil(PlanView v,
     }
     // ---------------- phase C ----------------
     {
-      const int r = tid / (64 * WPR);                 // row of this wavefront group
+      const int r = __builtin_amdgcn_readfirstlane(tid / (64 * WPR));   // row of this wavefront group
       const int item = tid % (64 * WPR);
       const int i1 = row0 + r;
       if (r < rows && item < S::ITEMS_ROW) {
@@ -254,34 +291,35 @@ __global__ __launch_bounds__((Shape<P, T, STIFF>::NT)) void k_pencil(PlanView v,
         int qs1, qc1, is1, ic1;
         q_range(i1, P, d1.nel, qs1, qc1);
         i_range(i1, P, n1, is1, ic1);
-        const double* __restrict__ w1 = d1.w + size_t(i1) * QC;
-        const size_t w1o = size_t(n1) * QC;
-        const T* __restrict__ B1 = bt_table<T>(d1) + size_t(i1) * IC * QC;
-        const size_t B1a = size_t(n1) * IC * QC;
+        const T* __restrict__ w1 = wt_t<T>(d1) + size_t(i1) * QC * 4;        // [qq1][o]
+        const T* __restrict__ B1 = bt_t<T>(d1) + size_t(i1) * QC * IC * 2;   // [qq1][jj1][a]
         T acc[J1P];
 #pragma unroll
         for (int k = 0; k < J1P; ++k) acc[k] = T(0);
         if (u3 < nj3 && jj2 < ic2) {
-          for (int qq1 = 0; qq1 < qc1; ++qq1) {
-            const int q1 = qs1 + qq1;
-            const T* rg = ring + (size_t(q1 % W) * NG * IC + jj2) * J3C + u3;
-            T H0, H1;
-            if constexpr (STIFF) {
-              const T g00 = rg[0 * IC * J3C], g10 = rg[1 * IC * J3C];
-              const T g01 = rg[2 * IC * J3C], g11 = rg[3 * IC * J3C];
-              H0 = T(w1[R00 * w1o + qq1]) * g00 + T(w1[R01 * w1o + qq1]) * g01;
-              H1 = T(w1[R10 * w1o + qq1]) * g10 + T(w1[R11 * w1o + qq1]) * g11;
-            } else {
-              H0 = T(w1[qq1]) * rg[0];
-              H1 = T(0);
-            }
+WQ_UNROLL(WQ_UNROLL_BC)
+          for (int qq1 = 0; qq1 < QC; ++qq1) {
+            if (qq1 < qc1) {   // uniform per wavefront
+              const int q1 = qs1 + qq1;
+              const T* rg = ring + (size_t(q1 % W) * NG * IC + jj2) * J3C + u3;
+              const T* wq = w1 + __builtin_amdgcn_readfirstlane(qq1 * 4);
+              T H0, H1;
+              if constexpr (STIFF) {
+                const T g00 = rg[0 * IC * J3C], g10 = rg[1 * IC * J3C];
+                const T g01 = rg[2 * IC * J3C], g11 = rg[3 * IC * J3C];
+                H0 = wq[R00] * g00 + wq[R01] * g01;
+                H1 = wq[R10] * g10 + wq[R11] * g11;
+              } else {
+                H0 = wq[R00] * rg[0];
+                H1 = T(0);
+              }
+              const T* b = B1 + __builtin_amdgcn_readfirstlane((qq1 * IC + part * J1P) * 2);
 #pragma unroll
-            for (int k = 0; k < J1P; ++k) {
-              const int jj1 = part * J1P + k;
-              if (jj1 < IC) {
-                const T* b = B1 + jj1 * QC + qq1;
-                if constexpr (STIFF) acc[k] += b[0] * H0 + b[B1a] * H1;
-                else acc[k] += b[0] * H0;
+              for (int k = 0; k < J1P; ++k) {
+                if (part * J1P + k < IC) {
+                  if constexpr (STIFF) acc[k] += b[2 * k] * H0 + b[2 * k + 1] * H1;
+                  else acc[k] += b[2 * k] * H0;
+                }
               }
             }
           }

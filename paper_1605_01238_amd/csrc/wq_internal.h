@@ -67,11 +67,21 @@ struct DirView {
   double* bd;            // nq * (p+1) derivatives
   double* bw;            // nq * p  p N_{i,p-1}(x_q) / (xi_{i+p} - xi_i), i = qspan+1 .. qspan+p
   double* w;             // 4 * n * qcap   weights, pair = 2*beta + alpha
-  double* op64;          // 4 * n * icap * qcap   T[j][q] = B^(alpha)_j(x_q) w_q
+  // Tables of the contraction, laid out so that everything one quadrature
+  // point qq of function i needs is contiguous (wide scalar loads):
+  double* op64;          // [n][qcap][icap][4]  T^(o)[jj][qq] = B^(alpha)_{is+jj}(x_{qs+qq}) w^(o)_qq, o = 2*beta + alpha
   float* op32;           // same in FP32
-  double* bt64;          // 2 * n * icap * qcap   B^(alpha)_{is+jj}(x_{qs+qq})
+  double* bt64;          // [n][qcap][icap][2]  B^(alpha)_{is+jj}(x_{qs+qq})
   float* bt32;
+  double* wt64;          // [n][qcap][4]        w^(o)_qq
+  float* wt32;
   int64_t* prefix;       // n + 1  prefix sums of #I_i
+  // Per quadrature point q (span e = qspan[q]), for the rows i = e + s,
+  // s = 0..p, whose support contains x_q: their four weights at x_q (0 if x_q
+  // is not in Q_i or i >= n), then B_{e+r}(x_q) and B'_{e+r}(x_q), r = 0..p:
+  // [nq][6(p+1)] = { w[s][o] (4(p+1)), b0[r] (p+1), b1[r] (p+1) }.
+  double* colt64;
+  float* colt32;
 };
 
 struct PlanView {
@@ -86,7 +96,7 @@ struct PlanView {
 };
 
 struct Layout {
-  size_t knots[3], x[3], qspan[3], bv[3], bd[3], bw[3], w[3], op64[3], op32[3], bt64[3], bt32[3], prefix[3];
+  size_t knots[3], x[3], qspan[3], bv[3], bd[3], bw[3], w[3], op64[3], op32[3], bt64[3], bt32[3], wt64[3], wt32[3], prefix[3], colt64[3], colt32[3];
   size_t field, ctrl, dctrl, flags, total;
 };
 
@@ -110,6 +120,7 @@ namespace wq {
 hipError_t launch_points(const PlanView& v, hipStream_t s);
 hipError_t launch_rules(const PlanView& v, hipStream_t s);
 hipError_t launch_ctrl_diff(const PlanView& v, hipStream_t s);
+hipError_t launch_coltab(const PlanView& v, hipStream_t s);
 hipError_t launch_geometry(const PlanView& v, const double* coef, double* xphys_out, hipStream_t s);
 hipError_t launch_pattern(const PlanView& v, int64_t* row_ptr, int32_t* col_idx, hipStream_t s);
 hipError_t launch_assemble(const PlanView& v, int which, void* mass, void* stiff, hipStream_t s);

@@ -60,7 +60,11 @@ void compute_layout(wq_plan* pl) {
     L.op32[k] = take(4 * n * ic * qc * 4);
     L.bt64[k] = take(2 * n * ic * qc * 8);
     L.bt32[k] = take(2 * n * ic * qc * 4);
+    L.wt64[k] = take(4 * n * qc * 8);
+    L.wt32[k] = take(4 * n * qc * 4);
     L.prefix[k] = take((n + 1) * 8);
+    L.colt64[k] = take(nq * 6 * (p + 1) * 8);
+    L.colt32[k] = take(nq * 6 * (p + 1) * 4);
   }
   L.field = take(size_t(wq::kNumChannels) * size_t(pl->nqtot) * (pl->prec == WQ_FP64 ? 8 : 4));
   L.ctrl = take(size_t(pl->nrows) * 3 * 8);
@@ -91,7 +95,11 @@ wq::PlanView wq_plan::view() const {
     d.op32 = reinterpret_cast<float*>(ws + lay.op32[k]);
     d.bt64 = reinterpret_cast<double*>(ws + lay.bt64[k]);
     d.bt32 = reinterpret_cast<float*>(ws + lay.bt32[k]);
+    d.wt64 = reinterpret_cast<double*>(ws + lay.wt64[k]);
+    d.wt32 = reinterpret_cast<float*>(ws + lay.wt32[k]);
     d.prefix = reinterpret_cast<int64_t*>(ws + lay.prefix[k]);
+    d.colt64 = reinterpret_cast<double*>(ws + lay.colt64[k]);
+    d.colt32 = reinterpret_cast<float*>(ws + lay.colt32[k]);
   }
   v.field = ws + lay.field;
   v.ctrl = reinterpret_cast<double*>(ws + lay.ctrl);
@@ -214,6 +222,8 @@ wq_status wq_setup(wq_plan* plan, const double* ctrl_dev, const double* coef_dev
   if (e != hipSuccess) return hip_fail(plan, e, "wq_setup: control-net differences");
   e = wq::launch_rules(v, stream);
   if (e != hipSuccess) return hip_fail(plan, e, "wq_setup: univariate kernel");
+  e = wq::launch_coltab(v, stream);
+  if (e != hipSuccess) return hip_fail(plan, e, "wq_setup: column tables");
   e = wq::launch_geometry(v, coef_dev, nullptr, stream);
   if (e != hipSuccess) return hip_fail(plan, e, "wq_setup: geometry kernel");
   plan->setup_done = true;

@@ -373,22 +373,52 @@ __global__ __launch_bounds__(256) void k_rules(PlanView v) {
       atomicMin(&v.flags[FLAG_SOLVE_FIRST], (dir * 4 + pair) * n + i);
     }
   }
-  // outputs
+  // outputs (lane = local quadrature point qq; zero beyond #Q_i and #I_i)
   if (lane < QC) {
     d.w[(size_t(pair) * n + i) * QC + lane] = wq;
+    const size_t pq = size_t(i) * QC + lane;
+    d.wt64[pq * 4 + pair] = wq;
+    d.wt32[pq * 4 + pair] = float(wq);
 #pragma unroll
     for (int jj = 0; jj < IC; ++jj) {
       const double b = dd_to_double(A[al][jj][lane]);
       const double t = b * wq;
-      const size_t o = ((size_t(pair) * n + i) * IC + jj) * QC + lane;
-      d.op64[o] = t;
-      d.op32[o] = float(t);
+      d.op64[(pq * IC + jj) * 4 + pair] = t;
+      d.op32[(pq * IC + jj) * 4 + pair] = float(t);
       if (pair < 2) {   // the B^(alpha) tables, alpha = pair
-        d.bt64[o] = b;
-        d.bt32[o] = float(b);
+        d.bt64[(pq * IC + jj) * 2 + pair] = b;
+        d.bt32[(pq * IC + jj) * 2 + pair] = float(b);
       }
     }
   }
+}
+
+// Per-point tables of direction `blockIdx.y` (see DirView::colt64): one
+// thread per (q, entry).
+template <int P>
+__global__ __launch_bounds__(256) void k_coltab(PlanView v) {
+  constexpr int QC = 3 * P + 1, NCT = 6 * (P + 1);
+  const DirView d = v.dir[blockIdx.y];
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= d.nq * NCT) return;
+  const int q = t / NCT, k = t % NCT;
+  const int e = d.qspan[q];
+  double val;
+  if (k < 4 * (P + 1)) {
+    const int s = k / 4, o = k % 4, i = e + s;
+    val = 0.0;
+    if (i < d.n) {
+      int qs, qc;
+      q_range(i, P, d.nel, qs, qc);
+      if (q >= qs && q < qs + qc) val = d.w[(size_t(o) * d.n + i) * QC + (q - qs)];
+    }
+  } else if (k < 5 * (P + 1)) {
+    val = d.bv[q * (P + 1) + (k - 4 * (P + 1))];
+  } else {
+    val = d.bd[q * (P + 1) + (k - 5 * (P + 1))];
+  }
+  d.colt64[t] = val;
+  d.colt32[t] = float(val);
 }
 
 // Prefix sums of the 1D row lengths #I_i (one thread per direction).
@@ -628,6 +658,21 @@ hipError_t launch_ctrl_diff(const PlanView& v, hipStream_t s) {
   const int64_t N = int64_t(v.dir[0].n) * v.dir[1].n * v.dir[2].n * 3;
   hipLaunchKernelGGL(k_ctrl_diff, dim3(unsigned((N + 255) / 256)), dim3(256), 0, s, v);
   return hipGetLastError();
+}
+
+template <int P>
+hipError_t coltab_p(const PlanView& v, hipStream_t s) {
+  int maxq = 0;
+  for (int k = 0; k < 3; ++k) maxq = v.dir[k].nq > maxq ? v.dir[k].nq : maxq;
+  const int work = maxq * 6 * (P + 1);
+  hipLaunchKernelGGL(k_coltab<P>, dim3((work + 255) / 256, 3), dim3(256), 0, s, v);
+  return hipGetLastError();
+}
+
+hipError_t launch_coltab(const PlanView& v, hipStream_t s) {
+#define C(P) coltab_p<P>(v, s)
+  WQ_DISPATCH_P(v.p, C)
+#undef C
 }
 
 hipError_t launch_pattern(const PlanView& v, int64_t* row_ptr, int32_t* col_idx, hipStream_t s) {
