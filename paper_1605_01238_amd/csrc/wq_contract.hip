@@ -4,46 +4,54 @@
 // direction k uses the rule w^(alpha_k, beta_k) with alpha_k = [k == m]
 // (trial) and beta_k = [k == l] (test), applied to the coefficient c_lm.
 //
-// Work decomposition ("pencil" kernel).  A workgroup owns the rows
-// (i1 = 0..n1-1, i2, i3) of one pencil; they are consecutive rows, so the
-// pencil's output is one contiguous CSR segment.  For a pencil the operators
-// of directions 3 and 2 are fixed, so the contractions over q3 and q2 are
-// shared by all its rows and done once per quadrature column q1:
+// Work decomposition.  A workgroup owns a run of consecutive rows
+// (i1 = r0..r1-1, i2, i3) of one pencil -- one contiguous CSR segment --
+// restricted to a part of the trial index j3.  The operators of directions 3
+// and 2 are fixed along the pencil, so the contractions over q3 and q2 are
+// done once per quadrature column q1 and shared by all rows of the run:
 //
 //   phase A (items: q1, q2):  Y_c[j3] = sum_q3 T3_c[j3][q3] K_c(q1,q2,q3) for
 //            the 8 distinct (field, dir-3 rule) channels of the stiffness
-//            (1 for the mass); then the dir-2 weights are folded in:
-//            terms that will meet the same B2^(alpha) and the same dir-1 rule
-//            are summed after scaling by their weights w2 ("weight merge"),
-//            leaving 6 arrays H[q2][j3] (1 for the mass) in LDS.
+//            (1 for the mass); the dir-2 weights are folded in at once:
+//            terms that meet the same B2^(alpha) and the same dir-1 rule are
+//            summed after scaling by their weights ("weight merge"), leaving
+//            6 arrays H[q2][j3] (1 for the mass) in LDS.
 //   phase B (items: q1, j3, group):  G_g[j2][j3] = sum_q2 B2^(a)[j2][q2] H,
-//            one group per dir-1 rule (4 for the stiffness, 1 for the mass),
-//            into an LDS ring buffer indexed by q1.
-//   phase C (items: row, j2, j3, j1-part):  for each row i1, once all q1 in
-//            Q_i1 are in the ring,  out[j1][j2][j3] = sum_q1
-//            B1^(0)[j1][q1] (w1^(0,0) G_(0,0) + w1^(0,1) G_(0,1))
-//          + B1^(1)[j1][q1] (w1^(1,0) G_(1,0) + w1^(1,1) G_(1,1)),
-//            staged in LDS and stored coalesced.
+//            one group g = 2*beta + alpha per dir-1 rule (4 for the
+//            stiffness, 1 for the mass), into LDS.
+//   phase C (items: j2, j3; columns q1 in order):  the column q1 lies in the
+//            knot span e; it only touches the rows i1 = e..e+p (whose support
+//            holds x_q1) and, in each, only the trial functions j1 = e..e+p
+//            (nonzero at x_q1).  Each item keeps the p+1 open rows in
+//            registers, indexed relative to e, and adds
+//              B_j1(x_q1) (w^(0,0)_i1 G_(0,0) + w^(0,1)_i1 G_(0,1))
+//            + B'_j1(x_q1) (w^(1,0)_i1 G_(1,0) + w^(1,1)_i1 G_(1,1)).
+//            When e advances, row e is complete: it is staged in LDS and
+//            stored coalesced, and the open rows shift by one.
 //
-// All univariate operators, weights and B-spline tables are read with
-// wavefront-uniform addresses (scalar loads); only the coefficient field and
-// the LDS intermediates are per-lane data.  The j3 range can be split across
-// workgroups (SC parts) and, inside phases A/B, processed in SA sub-parts, to
-// fit the FP64 ring buffer into LDS at high degree.
+// A run of rows r0..r1-1 needs the columns of the spans max(0, r0-p) ..
+// min(n_el-1, r1-1); splitting a pencil into runs repeats the phases A and B
+// of p spans per run, which buys workgroups when a patch has few pencils.
+//
+// Uniform data (operators, weights, B-spline values) is read with scalar
+// loads from tables laid out contiguously per quadrature point.
 #include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <climits>
 
 #include "wq_internal.h"
 
-// Unroll factors of the quadrature loops of phases A and B/C (trade register
-// pressure against loads in flight).
-#ifndef WQ_UNROLL_A
-#define WQ_UNROLL_A 2
+// Field values are loaded for this many consecutive q3 before use (loads in
+// flight per lane in phase A).
+#ifndef WQ_KB
+#define WQ_KB 2
 #endif
-#ifndef WQ_UNROLL_BC
-#define WQ_UNROLL_BC 4
+// Pencils are split into runs of rows until the grid holds about this many
+// workgroups.
+#ifndef WQ_WG_TARGET
+#define WQ_WG_TARGET 2048
 #endif
-#define WQ_STR(x) #x
-#define WQ_UNROLL(n) _Pragma(WQ_STR(unroll n))
 
 namespace wq {
 namespace {
@@ -51,42 +59,36 @@ namespace {
 // Rule index o = 2*beta + alpha of the univariate tables.
 enum : int { R00 = 0, R10 = 1, R01 = 2, R11 = 3 };
 
-template <int P, typename T> struct PencilCfg;
-// SC: j3 parts over workgroups; SA: j3 sub-parts in phases A/B; NP1: j1 parts
-// in phase C; C: q1 columns per chunk; NT: threads per workgroup.
-template <> struct PencilCfg<2, double> { static constexpr int SC = 1, SA = 1, NP1 = 2, C = 16, NT = 256; };
-template <> struct PencilCfg<3, double> { static constexpr int SC = 1, SA = 2, NP1 = 1, C = 12, NT = 256; };
-template <> struct PencilCfg<4, double> { static constexpr int SC = 2, SA = 2, NP1 = 1, C = 8, NT = 384; };
-template <> struct PencilCfg<5, double> { static constexpr int SC = 2, SA = 2, NP1 = 2, C = 8, NT = 384; };
-template <> struct PencilCfg<6, double> { static constexpr int SC = 2, SA = 2, NP1 = 1, C = 8, NT = 256; };
-template <> struct PencilCfg<2, float> { static constexpr int SC = 1, SA = 1, NP1 = 2, C = 16, NT = 256; };
-template <> struct PencilCfg<3, float> { static constexpr int SC = 1, SA = 1, NP1 = 1, C = 16, NT = 256; };
-template <> struct PencilCfg<4, float> { static constexpr int SC = 1, SA = 1, NP1 = 2, C = 16, NT = 384; };
-template <> struct PencilCfg<5, float> { static constexpr int SC = 1, SA = 2, NP1 = 1, C = 12, NT = 256; };
-template <> struct PencilCfg<6, float> { static constexpr int SC = 1, SA = 2, NP1 = 1, C = 8, NT = 192; };
+// NW: wavefronts per workgroup; J3: trial indices j3 per workgroup (phase C
+// uses IC * J3 lanes); C: quadrature columns per chunk of phases A and B.
+template <int P, typename T> struct PushCfg;
+template <> struct PushCfg<2, double> { static constexpr int NW = 1, J3 = 5, C = 4; };
+template <> struct PushCfg<3, double> { static constexpr int NW = 1, J3 = 7, C = 4; };
+template <> struct PushCfg<4, double> { static constexpr int NW = 1, J3 = 5, C = 4; };
+template <> struct PushCfg<5, double> { static constexpr int NW = 2, J3 = 11, C = 2; };
+template <> struct PushCfg<6, double> { static constexpr int NW = 2, J3 = 7, C = 4; };
+template <> struct PushCfg<2, float> { static constexpr int NW = 1, J3 = 5, C = 8; };
+template <> struct PushCfg<3, float> { static constexpr int NW = 1, J3 = 7, C = 8; };
+template <> struct PushCfg<4, float> { static constexpr int NW = 1, J3 = 5, C = 8; };
+template <> struct PushCfg<5, float> { static constexpr int NW = 2, J3 = 11, C = 4; };
+template <> struct PushCfg<6, float> { static constexpr int NW = 2, J3 = 7, C = 8; };
 
 template <int P, typename T, bool STIFF>
 struct Shape {
-  using Cfg = PencilCfg<P, T>;
+  using Cfg = PushCfg<P, T>;
   static constexpr int IC = 2 * P + 1, QC = 3 * P + 1;
-  static constexpr int SC = Cfg::SC, SA = Cfg::SA, NP1 = Cfg::NP1, C = Cfg::C, NT = Cfg::NT;
-  static constexpr int J3C = (IC + SC - 1) / SC;          // j3 per workgroup
-  static constexpr int J3A = (J3C + SA - 1) / SA;         // j3 per phase-A/B sub-part
-  static constexpr int J1P = (IC + NP1 - 1) / NP1;        // j1 per phase-C item
-  static constexpr int ITEMS_ROW = NP1 * IC * J3C;        // phase-C items of one row
-  static constexpr int WPR = (ITEMS_ROW + 63) / 64;       // wavefronts per row
-  static constexpr int RB = NT / (64 * WPR);              // rows per phase-C pass
-  static constexpr int W = QC + 2 * (RB - 1) + C;         // ring capacity (columns)
+  static constexpr int NT = 64 * Cfg::NW, J3 = Cfg::J3, C = Cfg::C;
+  static constexpr int NPART = (IC + J3 - 1) / J3;        // j3 parts
   static constexpr int NG = STIFF ? 4 : 1;                // dir-1 rule groups
   static constexpr int NH = STIFF ? 6 : 1;                // merged dir-2 inputs
   static constexpr int NCH = STIFF ? 8 : 1;               // dir-3 channels
-  static constexpr size_t RING = size_t(W) * NG * IC * J3C;
-  static constexpr size_t HBUF = size_t(C) * NH * QC * J3A;
-  static constexpr size_t STAGE = size_t(RB) * IC * IC * J3C;
-  static constexpr size_t LDS_BYTES = (RING + HBUF + STAGE) * sizeof(T);
-  static_assert(RB >= 1, "a row must fit in one workgroup");
-  static_assert(NT % 64 == 0, "whole wavefronts");
-  static_assert(LDS_BYTES <= 160 * 1024, "LDS capacity");
+  static constexpr int NCT = 6 * (P + 1);                 // column-table entries
+  static constexpr size_t HBUF = size_t(C) * NH * QC * J3;
+  static constexpr size_t GBUF = size_t(C) * NG * IC * J3;
+  static constexpr size_t STAGE = size_t(J3) * IC * IC;
+  static constexpr size_t LDS_BYTES = (HBUF + GBUF + STAGE) * sizeof(T);
+  static_assert(IC * J3 <= NT, "one phase-C item per lane");
+  static_assert(LDS_BYTES <= 64 * 1024, "LDS budget per workgroup");
 };
 
 template <typename T>
@@ -104,276 +106,281 @@ __device__ inline const T* wt_t(const DirView& d) {
   if constexpr (sizeof(T) == 8) return reinterpret_cast<const T*>(d.wt64);
   else return reinterpret_cast<const T*>(d.wt32);
 }
+template <typename T>
+__device__ inline const T* colt_t(const DirView& d) {
+  if constexpr (sizeof(T) == 8) return reinterpret_cast<const T*>(d.colt64);
+  else return reinterpret_cast<const T*>(d.colt32);
+}
 
 template <int P, typename T, bool STIFF>
-__global__ __launch_bounds__((Shape<P, T, STIFF>::NT)) void k_pencil(PlanView v, T* __restrict__ out) {
+__global__ __launch_bounds__((Shape<P, T, STIFF>::NT)) void k_push(PlanView v, T* __restrict__ out, int nseg) {
   using S = Shape<P, T, STIFF>;
-  constexpr int IC = S::IC, QC = S::QC, C = S::C, NT = S::NT, J3C = S::J3C, J3A = S::J3A;
-  constexpr int J1P = S::J1P, NG = S::NG, NH = S::NH, W = S::W, RB = S::RB, WPR = S::WPR;
-  extern __shared__ __align__(16) unsigned char smem[];
-  T* ring = reinterpret_cast<T*>(smem);              // [W][NG][IC][J3C]   (slot, g, jj2, u3)
-  T* hbuf = ring + S::RING;                          // [C][NH][QC][J3A]   (c, h, qq2, u)
-  T* stage = hbuf + S::HBUF;                         // [RB][J3C][IC][IC]  (r, u3, jj2, jj1)
+  constexpr int IC = S::IC, QC = S::QC, C = S::C, NT = S::NT, J3 = S::J3;
+  constexpr int NG = S::NG, NH = S::NH, NCT = S::NCT;
+  __shared__ __align__(16) T hbuf[S::HBUF];     // [C][NH][QC][J3]   (c, h, qq2, u)
+  __shared__ __align__(16) T gbuf[S::GBUF];     // [C][NG][IC][J3]   (c, g, jj2, u)
+  __shared__ __align__(16) T stage[S::STAGE];   // one row: [u3][jj2][jj1]
 
   const DirView d1 = v.dir[0], d2 = v.dir[1], d3 = v.dir[2];
-  const int n1 = d1.n, n2 = d2.n, nq1 = d1.nq, nq2 = d2.nq;
+  const int n1 = d1.n, n2 = d2.n, nq1 = d1.nq, nq2 = d2.nq, nel1 = d1.nel;
   const int tid = threadIdx.x;
-  const int pencil = blockIdx.x;
-  const int i2 = pencil % n2, i3 = pencil / n2;
+  // XCD-aware order: workgroups are dealt round-robin to the 8 XCDs; give
+  // each XCD a contiguous range of work items so that neighbouring pencils,
+  // which read overlapping coefficient blocks, share an L2.
+  const int total = gridDim.x, L = blockIdx.x;
+  const int xcd = L % 8, kx = L / 8, m8 = total / 8, r8 = total % 8;
+  int item = xcd * m8 + min(xcd, r8) + kx;
+  const int part = item % S::NPART;
+  item /= S::NPART;
+  const int i2 = item % n2;
+  item /= n2;
+  const int seg = item % nseg, i3 = item / nseg;
+
   int qs2, qc2, qs3, qc3, is2, ic2, is3, ic3;
   q_range(i2, P, d2.nel, qs2, qc2);
   q_range(i3, P, d3.nel, qs3, qc3);
   i_range(i2, P, n2, is2, ic2);
   i_range(i3, P, d3.n, is3, ic3);
-  // this workgroup's j3 range [j3lo, j3lo + nj3)
-  const int j3lo = blockIdx.y * J3C;
-  const int nj3 = min(J3C, ic3 - j3lo);
+  const int j3lo = part * J3;
+  const int nj3 = min(J3, ic3 - j3lo);
   if (nj3 <= 0) return;   // uniform per workgroup
+
+  // rows r0..r1-1 need the columns of spans e0..e1
+  const int r0 = int(int64_t(seg) * n1 / nseg), r1 = int(int64_t(seg + 1) * n1 / nseg);
+  const int e0 = max(0, r0 - P), e1 = min(nel1 - 1, r1 - 1);
+  const int qbeg = e0 == 0 ? 0 : P + 2 * e0 - 1;        // knot chi_e0 opens span e0
+  const int qend = e1 == nel1 - 1 ? nq1 : P + 2 * e1 + 1;
 
   const int64_t N = v.nqtot;
   const T* __restrict__ field = static_cast<const T*>(v.field);
-  // pencil-constant tables (uniform addresses -> scalar loads)
   const T* __restrict__ T3 = op_t<T>(d3) + size_t(i3) * QC * IC * 4;    // [qq3][jj3][o]
   const T* __restrict__ w2 = wt_t<T>(d2) + size_t(i2) * QC * 4;         // [qq2][o]
   const T* __restrict__ B2 = bt_t<T>(d2) + size_t(i2) * QC * IC * 2;    // [qq2][jj2][a]
+  const T* __restrict__ CT = colt_t<T>(d1);                             // [q1][NCT]
+  const int* __restrict__ span1 = d1.qspan;
 
   // CSR position of row (i1, i2, i3): closed-form prefix of the row lengths
   const int64_t Tn1 = d1.prefix[n1], Tn2 = d2.prefix[n2];
   const int64_t pencil_start = d3.prefix[i3] * Tn2 * Tn1 + int64_t(ic3) * d2.prefix[i2] * Tn1;
-  const int64_t row_mult = int64_t(ic3) * ic2;      // row start = pencil_start + row_mult * prefix1[i1]
+  const int64_t row_mult = int64_t(ic3) * ic2;
 
-  int next_col = 0;
-  for (int row0 = 0; row0 < n1; row0 += RB) {
-    const int rows = min(RB, n1 - row0);
-    int qsl, qcl;
-    q_range(row0 + rows - 1, P, d1.nel, qsl, qcl);
-    const int need_hi = qsl + qcl - 1;                // last column the batch needs
-    // ---- produce columns until the batch's window is in the ring ----
-    while (next_col <= need_hi) {
-      const int col0 = next_col;
-      for (int sub = 0; sub < J3C; sub += J3A) {     // j3 sub-parts of phases A/B
-        const int ua = sub, na = min(J3A, nj3 - sub); // u in [ua, ua + na) within this WG's range
-        if (na <= 0) break;
-        // ---------------- phase A ----------------
-        for (int it = tid; it < C * QC; it += NT) {
-          const int c = it % C, qq2 = it / C;
-          const int q1 = col0 + c;
-          if (q1 >= nq1 || qq2 >= qc2) continue;
-          const int q2 = qs2 + qq2;
-          T Y[S::NCH][J3A];
+  // phase-C role of this lane: (jj2, u3)
+  const int cj2 = tid % IC, cu3 = tid / IC;
+  const bool cl = tid < IC * J3 && cj2 < ic2 && cu3 < nj3;
+  T acc[P + 1][2 * P + 1];   // open rows e+s, s = 0..P; trial offset d = j1 - (e+s) + P
 #pragma unroll
-          for (int ch = 0; ch < S::NCH; ++ch)
+  for (int s = 0; s <= P; ++s)
 #pragma unroll
-            for (int u = 0; u < J3A; ++u) Y[ch][u] = T(0);
-          const T* f = field + q1 + int64_t(nq1) * (q2 + int64_t(nq2) * qs3);
-          const int64_t fstride = int64_t(nq1) * nq2;
-          // field values are loaded for KB consecutive q3 before they are used,
-          // so that several loads are in flight per lane
-          constexpr int KB = 4;
-          constexpr int NF = STIFF ? 6 : 1;
+    for (int d = 0; d <= 2 * P; ++d) acc[s][d] = T(0);
+
+  // row i1 (slot 0) is complete: store it if it is ours, then shift the slots
+  auto flush = [&](int i1) {
+    if (i1 >= r0 && i1 < r1) {   // uniform
+      const int dlo = i1 < P ? P - i1 : 0;
+      const int dhi = min(2 * P, P + n1 - 1 - i1);
+      const int ic1 = dhi - dlo + 1;
+      if (cl) {
+#pragma unroll
+        for (int d = 0; d <= 2 * P; ++d)
+          if (d >= dlo && d <= dhi) stage[(cu3 * ic2 + cj2) * ic1 + (d - dlo)] = acc[0][d];
+      }
+      __syncthreads();
+      const int seglen = ic1 * ic2;
+      T* o = out + pencil_start + row_mult * d1.prefix[i1] + int64_t(j3lo) * seglen;
+      const int len = nj3 * seglen;
+      for (int t = tid; t < len; t += NT) o[t] = stage[t];
+      __syncthreads();
+    }
+#pragma unroll
+    for (int s = 0; s < P; ++s)
+#pragma unroll
+      for (int d = 0; d <= 2 * P; ++d) acc[s][d] = acc[s + 1][d];
+#pragma unroll
+    for (int d = 0; d <= 2 * P; ++d) acc[P][d] = T(0);
+  };
+
+  int e_cur = e0;
+  for (int col0 = qbeg; col0 < qend; col0 += C) {
+    // ---------------- phase A ----------------
+    for (int it = tid; it < C * QC; it += NT) {
+      const int c = it % C, qq2 = it / C;
+      const int q1 = col0 + c;
+      if (q1 >= qend || qq2 >= qc2) continue;
+      const int q2 = qs2 + qq2;
+      T Y[S::NCH][J3];
+#pragma unroll
+      for (int ch = 0; ch < S::NCH; ++ch)
+#pragma unroll
+        for (int u = 0; u < J3; ++u) Y[ch][u] = T(0);
+      const T* f = field + q1 + int64_t(nq1) * (q2 + int64_t(nq2) * qs3);
+      const int64_t fstride = int64_t(nq1) * nq2;
+      constexpr int KB = WQ_KB;
+      constexpr int NF = STIFF ? 6 : 1;
 #pragma unroll 1
-          for (int b0 = 0; b0 < QC; b0 += KB) {
-            if (b0 < qc3) {   // uniform
-              T kv[KB][NF];
+      for (int b0 = 0; b0 < QC; b0 += KB) {
+        if (b0 < qc3) {   // uniform
+          T kv[KB][NF];
 #pragma unroll
-              for (int kb = 0; kb < KB; ++kb) {
-                const int qq3 = b0 + kb;
-                if (qq3 < qc3) {
-                  const T* fk = f + qq3 * fstride;
+          for (int kb = 0; kb < KB; ++kb) {
+            const int qq3 = b0 + kb;
+            if (qq3 < qc3) {
+              const T* fk = f + qq3 * fstride;
 #pragma unroll
-                  for (int fi = 0; fi < NF; ++fi) kv[kb][fi] = fk[(STIFF ? fi + 1 : 0) * N];
-                } else {
+              for (int fi = 0; fi < NF; ++fi) kv[kb][fi] = fk[(STIFF ? fi + 1 : 0) * N];
+            } else {
 #pragma unroll
-                  for (int fi = 0; fi < NF; ++fi) kv[kb][fi] = T(0);
-                }
-              }
+              for (int fi = 0; fi < NF; ++fi) kv[kb][fi] = T(0);
+            }
+          }
 #pragma unroll
-              for (int kb = 0; kb < KB; ++kb) {
-                const int qq3 = b0 + kb;
-                if (qq3 < qc3) {   // uniform
-                  const T* t = T3 + __builtin_amdgcn_readfirstlane((qq3 * IC + j3lo + ua) * 4);
-                  if constexpr (STIFF) {
-                    const T k11 = kv[kb][0], k22 = kv[kb][1], k33 = kv[kb][2];
-                    const T k12 = kv[kb][3], k13 = kv[kb][4], k23 = kv[kb][5];
+          for (int kb = 0; kb < KB; ++kb) {
+            const int qq3 = b0 + kb;
+            if (qq3 < qc3) {   // uniform
+              const T* t = T3 + __builtin_amdgcn_readfirstlane((qq3 * IC + j3lo) * 4);
+              if constexpr (STIFF) {
+                const T k11 = kv[kb][0], k22 = kv[kb][1], k33 = kv[kb][2];
+                const T k12 = kv[kb][3], k13 = kv[kb][4], k23 = kv[kb][5];
 #pragma unroll
-                    for (int u = 0; u < J3A; ++u) {
-                      if (j3lo + ua + u < IC) {   // uniform
-                        const T t0 = t[u * 4 + R00], t1 = t[u * 4 + R10], t2 = t[u * 4 + R01], t3 = t[u * 4 + R11];
-                        Y[0][u] += t0 * k11;
-                        Y[1][u] += t0 * k22;
-                        Y[2][u] += t3 * k33;
-                        Y[3][u] += t0 * k12;
-                        Y[4][u] += t1 * k13;
-                        Y[5][u] += t2 * k13;
-                        Y[6][u] += t1 * k23;
-                        Y[7][u] += t2 * k23;
-                      }
-                    }
-                  } else {
-#pragma unroll
-                    for (int u = 0; u < J3A; ++u)
-                      if (j3lo + ua + u < IC) Y[0][u] += t[u * 4 + R00] * kv[kb][0];
+                for (int u = 0; u < J3; ++u) {
+                  if (j3lo + u < IC) {   // uniform
+                    const T t0 = t[u * 4 + R00], t1 = t[u * 4 + R10], t2 = t[u * 4 + R01], t3 = t[u * 4 + R11];
+                    Y[0][u] += t0 * k11;
+                    Y[1][u] += t0 * k22;
+                    Y[2][u] += t3 * k33;
+                    Y[3][u] += t0 * k12;
+                    Y[4][u] += t1 * k13;
+                    Y[5][u] += t2 * k13;
+                    Y[6][u] += t1 * k23;
+                    Y[7][u] += t2 * k23;
                   }
                 }
-              }
-            }
-          }
-          // fold in the dir-2 weights of this q2 (weight merge)
-          T* h = hbuf + (size_t(c) * NH * QC + qq2) * J3A;
-          if constexpr (STIFF) {
-            const T a0 = w2[qq2 * 4 + R00], a1 = w2[qq2 * 4 + R10];
-            const T a2 = w2[qq2 * 4 + R01], a3 = w2[qq2 * 4 + R11];
-#pragma unroll
-            for (int u = 0; u < J3A; ++u) {
-              h[0 * QC * J3A + u] = a3 * Y[1][u] + a1 * Y[7][u];   // -> G_(0,0) through B2^(1)
-              h[1 * QC * J3A + u] = a0 * Y[2][u] + a2 * Y[6][u];   // -> G_(0,0) through B2^(0)
-              h[2 * QC * J3A + u] = a0 * Y[0][u];                  // -> G_(1,1) through B2^(0)
-              h[3 * QC * J3A + u] = a1 * Y[3][u];                  // -> G_(0,1) through B2^(1)
-              h[4 * QC * J3A + u] = a0 * Y[4][u];                  // -> G_(0,1) through B2^(0)
-              h[5 * QC * J3A + u] = a2 * Y[3][u] + a0 * Y[5][u];   // -> G_(1,0) through B2^(0)
-            }
-          } else {
-            const T a0 = w2[qq2 * 4 + R00];
-#pragma unroll
-            for (int u = 0; u < J3A; ++u) h[u] = a0 * Y[0][u];
-          }
-        }
-        __syncthreads();
-        // ---------------- phase B ----------------
-        // item: (u, c, g); group g: 0 = G_(0,0), 1 = G_(1,0), 2 = G_(0,1), 3 = G_(1,1)
-        for (int it = tid; it < J3A * C * NG; it += NT) {
-          const int u = it % J3A, c = (it / J3A) % C, g = it / (J3A * C);
-          const int q1 = col0 + c;
-          if (q1 >= nq1 || u >= na) continue;
-          // inputs through B2^(1) (h1) and B2^(0) (h0); -1 = none
-          int h1, h0;
-          if constexpr (STIFF) {
-            h1 = g == 0 ? 0 : (g == 2 ? 3 : -1);
-            h0 = g == 0 ? 1 : (g == 1 ? 5 : (g == 2 ? 4 : 2));
-          } else {
-            h1 = -1;
-            h0 = 0;
-          }
-          T G[IC];
-#pragma unroll
-          for (int jj2 = 0; jj2 < IC; ++jj2) G[jj2] = T(0);
-          const T* hb = hbuf + size_t(c) * NH * QC * J3A + u;
-WQ_UNROLL(WQ_UNROLL_BC)
-          for (int qq2 = 0; qq2 < QC; ++qq2) {
-            if (qq2 < qc2) {   // uniform
-              const T x0 = hb[(h0 * QC + qq2) * J3A];
-              const T x1 = h1 >= 0 ? hb[(h1 * QC + qq2) * J3A] : T(0);
-              const T* b = B2 + __builtin_amdgcn_readfirstlane(qq2 * IC * 2);
-#pragma unroll
-              for (int jj2 = 0; jj2 < IC; ++jj2) {
-                if constexpr (STIFF) G[jj2] += b[jj2 * 2] * x0 + b[jj2 * 2 + 1] * x1;
-                else G[jj2] += b[jj2 * 2] * x0;
-              }
-            }
-          }
-          T* r = ring + ((size_t(q1 % W) * NG + g) * IC) * J3C + ua + u;
-#pragma unroll
-          for (int jj2 = 0; jj2 < IC; ++jj2) r[jj2 * J3C] = G[jj2];
-        }
-        __syncthreads();
-      }
-      next_col += C;
-    }
-    // ---------------- phase C ----------------
-    {
-      const int r = __builtin_amdgcn_readfirstlane(tid / (64 * WPR));   // row of this wavefront group
-      const int item = tid % (64 * WPR);
-      const int i1 = row0 + r;
-      if (r < rows && item < S::ITEMS_ROW) {
-        const int jj2 = item % IC;
-        const int u3 = (item / IC) % J3C;
-        const int part = item / (IC * J3C);
-        int qs1, qc1, is1, ic1;
-        q_range(i1, P, d1.nel, qs1, qc1);
-        i_range(i1, P, n1, is1, ic1);
-        const T* __restrict__ w1 = wt_t<T>(d1) + size_t(i1) * QC * 4;        // [qq1][o]
-        const T* __restrict__ B1 = bt_t<T>(d1) + size_t(i1) * QC * IC * 2;   // [qq1][jj1][a]
-        T acc[J1P];
-#pragma unroll
-        for (int k = 0; k < J1P; ++k) acc[k] = T(0);
-        if (u3 < nj3 && jj2 < ic2) {
-WQ_UNROLL(WQ_UNROLL_BC)
-          for (int qq1 = 0; qq1 < QC; ++qq1) {
-            if (qq1 < qc1) {   // uniform per wavefront
-              const int q1 = qs1 + qq1;
-              const T* rg = ring + (size_t(q1 % W) * NG * IC + jj2) * J3C + u3;
-              const T* wq = w1 + __builtin_amdgcn_readfirstlane(qq1 * 4);
-              T H0, H1;
-              if constexpr (STIFF) {
-                const T g00 = rg[0 * IC * J3C], g10 = rg[1 * IC * J3C];
-                const T g01 = rg[2 * IC * J3C], g11 = rg[3 * IC * J3C];
-                H0 = wq[R00] * g00 + wq[R01] * g01;
-                H1 = wq[R10] * g10 + wq[R11] * g11;
               } else {
-                H0 = wq[R00] * rg[0];
-                H1 = T(0);
-              }
-              const T* b = B1 + __builtin_amdgcn_readfirstlane((qq1 * IC + part * J1P) * 2);
 #pragma unroll
-              for (int k = 0; k < J1P; ++k) {
-                if (part * J1P + k < IC) {
-                  if constexpr (STIFF) acc[k] += b[2 * k] * H0 + b[2 * k + 1] * H1;
-                  else acc[k] += b[2 * k] * H0;
-                }
+                for (int u = 0; u < J3; ++u)
+                  if (j3lo + u < IC) Y[0][u] += t[u * 4 + R00] * kv[kb][0];
               }
             }
           }
-          T* st = stage + (size_t(r) * J3C + u3) * IC * IC + jj2 * IC;
-#pragma unroll
-          for (int k = 0; k < J1P; ++k) {
-            const int jj1 = part * J1P + k;
-            if (jj1 < ic1) st[jj1] = acc[k];
-          }
         }
+      }
+      // fold in the dir-2 weights of this q2 (weight merge)
+      T* h = hbuf + (size_t(c) * NH * QC + qq2) * J3;
+      if constexpr (STIFF) {
+        const T* a = w2 + qq2 * 4;
+        const T a0 = a[R00], a1 = a[R10], a2 = a[R01], a3 = a[R11];
+#pragma unroll
+        for (int u = 0; u < J3; ++u) {
+          h[0 * QC * J3 + u] = a3 * Y[1][u] + a1 * Y[7][u];   // -> G_(0,0) through B2^(1)
+          h[1 * QC * J3 + u] = a0 * Y[2][u] + a2 * Y[6][u];   // -> G_(0,0) through B2^(0)
+          h[2 * QC * J3 + u] = a0 * Y[0][u];                  // -> G_(1,1) through B2^(0)
+          h[3 * QC * J3 + u] = a1 * Y[3][u];                  // -> G_(0,1) through B2^(1)
+          h[4 * QC * J3 + u] = a0 * Y[4][u];                  // -> G_(0,1) through B2^(0)
+          h[5 * QC * J3 + u] = a2 * Y[3][u] + a0 * Y[5][u];   // -> G_(1,0) through B2^(0)
+        }
+      } else {
+        const T a0 = w2[qq2 * 4 + R00];
+#pragma unroll
+        for (int u = 0; u < J3; ++u) h[u] = a0 * Y[0][u];
       }
     }
     __syncthreads();
-    // ---- coalesced store of the batch: each row's j3 range is contiguous ----
-    for (int r = 0; r < rows; ++r) {
-      const int i1 = row0 + r;
-      int is1, ic1;
-      i_range(i1, P, n1, is1, ic1);
-      const int seg = ic1 * ic2;                      // values per j3 slice of the row
-      const int64_t base = pencil_start + row_mult * d1.prefix[i1] + int64_t(j3lo) * seg;
-      const int len = nj3 * seg;
-      for (int t = tid; t < len; t += NT) {
-        const int u3 = t / seg, rem = t % seg, jj2 = rem / ic1, jj1 = rem % ic1;
-        out[base + t] = stage[((size_t(r) * J3C + u3) * IC + jj2) * IC + jj1];
+    // ---------------- phase B ----------------
+    // item (u, c, g); group g: 0 = G_(0,0), 1 = G_(1,0), 2 = G_(0,1), 3 = G_(1,1)
+    for (int it = tid; it < J3 * C * NG; it += NT) {
+      const int u = it % J3, c = (it / J3) % C, g = it / (J3 * C);
+      const int q1 = col0 + c;
+      if (q1 >= qend || u >= nj3) continue;
+      int h1, h0;   // inputs through B2^(1) and B2^(0); -1 = none
+      if constexpr (STIFF) {
+        h1 = g == 0 ? 0 : (g == 2 ? 3 : -1);
+        h0 = g == 0 ? 1 : (g == 1 ? 5 : (g == 2 ? 4 : 2));
+      } else {
+        h1 = -1;
+        h0 = 0;
+      }
+      T G[IC];
+#pragma unroll
+      for (int jj2 = 0; jj2 < IC; ++jj2) G[jj2] = T(0);
+      const T* hb = hbuf + size_t(c) * NH * QC * J3 + u;
+#pragma unroll 4
+      for (int qq2 = 0; qq2 < QC; ++qq2) {
+        if (qq2 < qc2) {   // uniform
+          const T x0 = hb[(h0 * QC + qq2) * J3];
+          const T x1 = h1 >= 0 ? hb[(h1 * QC + qq2) * J3] : T(0);
+          const T* b = B2 + __builtin_amdgcn_readfirstlane(qq2 * IC * 2);
+#pragma unroll
+          for (int jj2 = 0; jj2 < IC; ++jj2) {
+            if constexpr (STIFF) G[jj2] += b[jj2 * 2] * x0 + b[jj2 * 2 + 1] * x1;
+            else G[jj2] += b[jj2 * 2] * x0;
+          }
+        }
+      }
+      T* gb = gbuf + (size_t(c * NG + g) * IC) * J3 + u;
+#pragma unroll
+      for (int jj2 = 0; jj2 < IC; ++jj2) gb[jj2 * J3] = G[jj2];
+    }
+    __syncthreads();
+    // ---------------- phase C ----------------
+    for (int c = 0; c < C; ++c) {
+      const int q1 = col0 + c;
+      if (q1 >= qend) break;   // uniform
+      const int e = span1[q1];
+      while (e_cur < e) {      // uniform; rows before e are complete
+        flush(e_cur);
+        ++e_cur;
+      }
+      if (cl) {
+        const T* ct = CT + __builtin_amdgcn_readfirstlane(q1 * NCT);
+        const T* gb = gbuf + (size_t(c * NG) * IC + cj2) * J3 + cu3;
+        if constexpr (STIFF) {
+          const T g00 = gb[0 * IC * J3], g10 = gb[1 * IC * J3], g01 = gb[2 * IC * J3], g11 = gb[3 * IC * J3];
+#pragma unroll
+          for (int s = 0; s <= P; ++s) {
+            const T* w = ct + s * 4;
+            const T H0 = w[R00] * g00 + w[R01] * g01;
+            const T H1 = w[R10] * g10 + w[R11] * g11;
+#pragma unroll
+            for (int r = 0; r <= P; ++r)
+              acc[s][r - s + P] += ct[4 * (P + 1) + r] * H0 + ct[5 * (P + 1) + r] * H1;
+          }
+        } else {
+          const T g0 = gb[0];
+#pragma unroll
+          for (int s = 0; s <= P; ++s) {
+            const T H0 = ct[s * 4 + R00] * g0;
+#pragma unroll
+            for (int r = 0; r <= P; ++r) acc[s][r - s + P] += ct[4 * (P + 1) + r] * H0;
+          }
+        }
       }
     }
     __syncthreads();
   }
+  // the rows still open
+  for (int s = 0; s <= P; ++s) flush(e_cur + s);
 }
 
 template <int P, typename T, bool STIFF>
-hipError_t pencil_launch(const PlanView& v, void* out, hipStream_t s) {
+hipError_t push_launch(const PlanView& v, void* out, hipStream_t s) {
   using Sh = Shape<P, T, STIFF>;
-  const int n2 = v.dir[1].n, n3 = v.dir[2].n;
-  dim3 grid(unsigned(n2 * n3), unsigned(Sh::SC));
-  static bool attr_set = false;   // dynamic LDS above the default limit must be opted into
-  if (!attr_set) {
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_pencil<P, T, STIFF>),
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, int(Sh::LDS_BYTES));
-    if (e != hipSuccess) return e;
-    attr_set = true;
-  }
-  hipLaunchKernelGGL((k_pencil<P, T, STIFF>), grid, dim3(Sh::NT), Sh::LDS_BYTES, s, v, static_cast<T*>(out));
+  const int64_t wgs = int64_t(v.dir[1].n) * v.dir[2].n * Sh::NPART;
+  // runs of at least 2p rows
+  const int max_seg = std::max(1, v.dir[0].n / (2 * P));
+  const int nseg = int(std::min<int64_t>(max_seg, std::max<int64_t>(1, (WQ_WG_TARGET + wgs - 1) / wgs)));
+  const int64_t items = wgs * nseg;
+  if (items <= 0 || items > INT32_MAX) return hipErrorInvalidConfiguration;
+  hipLaunchKernelGGL((k_push<P, T, STIFF>), dim3(unsigned(items)), dim3(Sh::NT), 0, s, v, static_cast<T*>(out), nseg);
   return hipGetLastError();
 }
 
 template <int P, typename T>
 hipError_t assemble_pt(const PlanView& v, int which, void* mass, void* stiff, hipStream_t s) {
   if (which & WQ_MASS) {
-    hipError_t e = pencil_launch<P, T, false>(v, mass, s);
+    hipError_t e = push_launch<P, T, false>(v, mass, s);
     if (e != hipSuccess) return e;
   }
   if (which & WQ_STIFF) {
-    hipError_t e = pencil_launch<P, T, true>(v, stiff, s);
+    hipError_t e = push_launch<P, T, true>(v, stiff, s);
     if (e != hipSuccess) return e;
   }
   return hipSuccess;
