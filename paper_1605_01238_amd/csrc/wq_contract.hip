@@ -4,15 +4,16 @@
 // direction k uses the rule w^(alpha_k, beta_k) with alpha_k = [k == m]
 // (trial) and beta_k = [k == l] (test), applied to the coefficient c_lm.
 //
-// Work decomposition.  A workgroup owns a run of consecutive rows
-// (i1 = r0..r1-1, i2, i3) of one pencil -- one contiguous CSR segment --
-// restricted to a part of the trial index j3.  The operators of directions 3
-// and 2 are fixed along the pencil, so the contractions over q3 and q2 are
-// done once per quadrature column q1 and shared by all rows of the run:
+// Work decomposition.  The first contraction (over q3) does not depend on
+// i1 or i2, so it is done once per test index i3 for the whole (q1, q2)
+// plane by k_first and kept in HBM.  A workgroup of the pencil kernel then
+// owns a run of consecutive rows (i1 = r0..r1-1, i2, i3) of one pencil -- one
+// contiguous CSR segment -- restricted to a part of the trial index j3.  The
+// operators of direction 2 are fixed along the pencil, so the contraction
+// over q2 is done once per quadrature column q1 and shared by all rows:
 //
-//   phase A (items: q1, q2):  Y_c[j3] = sum_q3 T3_c[j3][q3] K_c(q1,q2,q3) for
-//            the 8 distinct (field, dir-3 rule) channels of the stiffness
-//            (1 for the mass); the dir-2 weights are folded in at once:
+//   phase A (items: q1, q2, j3):  read the 8 channels Y_c[j3] of the first
+//            contraction (1 for the mass) and fold in the dir-2 weights:
 //            terms that meet the same B2^(alpha) and the same dir-1 rule are
 //            summed after scaling by their weights ("weight merge"), leaving
 //            6 arrays H[q2][j3] (1 for the mass) in LDS.
@@ -42,11 +43,6 @@
 
 #include "wq_internal.h"
 
-// Field values are loaded for this many consecutive q3 before use (loads in
-// flight per lane in phase A).
-#ifndef WQ_KB
-#define WQ_KB 2
-#endif
 // Pencils are split into runs of rows until the grid holds about this many
 // workgroups.
 #ifndef WQ_WG_TARGET
@@ -66,12 +62,12 @@ template <> struct PushCfg<2, double> { static constexpr int NW = 1, J3 = 5, C =
 template <> struct PushCfg<3, double> { static constexpr int NW = 1, J3 = 7, C = 4; };
 template <> struct PushCfg<4, double> { static constexpr int NW = 1, J3 = 5, C = 4; };
 template <> struct PushCfg<5, double> { static constexpr int NW = 2, J3 = 11, C = 2; };
-template <> struct PushCfg<6, double> { static constexpr int NW = 2, J3 = 7, C = 4; };
+template <> struct PushCfg<6, double> { static constexpr int NW = 2, J3 = 7, C = 2; };
 template <> struct PushCfg<2, float> { static constexpr int NW = 1, J3 = 5, C = 8; };
 template <> struct PushCfg<3, float> { static constexpr int NW = 1, J3 = 7, C = 8; };
 template <> struct PushCfg<4, float> { static constexpr int NW = 1, J3 = 5, C = 8; };
 template <> struct PushCfg<5, float> { static constexpr int NW = 2, J3 = 11, C = 4; };
-template <> struct PushCfg<6, float> { static constexpr int NW = 2, J3 = 7, C = 8; };
+template <> struct PushCfg<6, float> { static constexpr int NW = 2, J3 = 7, C = 4; };
 
 template <int P, typename T, bool STIFF>
 struct Shape {
@@ -80,7 +76,7 @@ struct Shape {
   static constexpr int NT = 64 * Cfg::NW, J3 = Cfg::J3, C = Cfg::C;
   static constexpr int NPART = (IC + J3 - 1) / J3;        // j3 parts
   static constexpr int NG = STIFF ? 4 : 1;                // dir-1 rule groups
-  static constexpr int NH = STIFF ? 6 : 1;                // merged dir-2 inputs
+  static constexpr int NH = STIFF ? 7 : 1;                // merged dir-2 inputs (+1 zero array)
   static constexpr int NCH = STIFF ? 8 : 1;               // dir-3 channels
   static constexpr int NCT = 6 * (P + 1);                 // column-table entries
   static constexpr size_t HBUF = size_t(C) * NH * QC * J3;
@@ -112,6 +108,100 @@ __device__ inline const T* colt_t(const DirView& d) {
   else return reinterpret_cast<const T*>(d.colt32);
 }
 
+// n consecutive values (n a multiple of the vector width, 16-byte aligned)
+template <typename T, int NV>
+__device__ inline void load_vec(const T* __restrict__ p, T (&out)[NV]) {
+  if constexpr (sizeof(T) == 8 && NV % 2 == 0) {
+#pragma unroll
+    for (int k = 0; k < NV / 2; ++k) {
+      const double2 x = reinterpret_cast<const double2*>(p)[k];
+      out[2 * k] = x.x;
+      out[2 * k + 1] = x.y;
+    }
+  } else if constexpr (sizeof(T) == 4 && NV % 4 == 0) {
+#pragma unroll
+    for (int k = 0; k < NV / 4; ++k) {
+      const float4 x = reinterpret_cast<const float4*>(p)[k];
+      out[4 * k] = x.x;
+      out[4 * k + 1] = x.y;
+      out[4 * k + 2] = x.z;
+      out[4 * k + 3] = x.w;
+    }
+  } else {
+#pragma unroll
+    for (int k = 0; k < NV; ++k) out[k] = p[k];
+  }
+}
+template <typename T, int NV>
+__device__ inline void store_vec(T* __restrict__ p, const T (&v)[NV]) {
+  if constexpr (sizeof(T) == 8 && NV % 2 == 0) {
+#pragma unroll
+    for (int k = 0; k < NV / 2; ++k) reinterpret_cast<double2*>(p)[k] = double2{v[2 * k], v[2 * k + 1]};
+  } else if constexpr (sizeof(T) == 4 && NV % 4 == 0) {
+#pragma unroll
+    for (int k = 0; k < NV / 4; ++k)
+      reinterpret_cast<float4*>(p)[k] = float4{v[4 * k], v[4 * k + 1], v[4 * k + 2], v[4 * k + 3]};
+  } else {
+#pragma unroll
+    for (int k = 0; k < NV; ++k) p[k] = v[k];
+  }
+}
+
+// First contraction, shared by all pencils with the same i3: for every
+// quadrature point (q1, q2) and every trial index j3 of I_i3,
+//   Y_c[j3] = sum_{q3 in Q_i3} B3^(alpha_c)_j3(x_q3) w3^(o_c)_{i3,q3} K_c(q1, q2, q3)
+// for the 8 channels c = (coefficient, dir-3 rule) of the stiffness
+// (K11 T^(0,0), K22 T^(0,0), K33 T^(1,1), K12 T^(0,0), K13 T^(1,0),
+//  K13 T^(0,1), K23 T^(1,0), K23 T^(0,1)) or the single det J T^(0,0) of
+// the mass.  Lanes run over the (q2, q1) plane, whose points are contiguous
+// in the field, so every load is coalesced; the record of a point,
+// [jj3][c], is stored contiguously for the pencil kernel.
+template <int P, typename T, bool STIFF>
+__global__ __launch_bounds__(256) void k_first(PlanView v) {
+  constexpr int IC = 2 * P + 1, QC = 3 * P + 1, NCH = STIFF ? kYChannels : 1;
+  const DirView d1 = v.dir[0], d2 = v.dir[1], d3 = v.dir[2];
+  const int64_t plane = int64_t(d1.nq) * d2.nq;
+  const int64_t l = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  const int i3 = blockIdx.y;
+  if (l >= plane) return;
+  int qs3, qc3;
+  q_range(i3, P, d3.nel, qs3, qc3);
+  const T* __restrict__ T3 = op_t<T>(d3) + size_t(i3) * QC * IC * 4;    // [qq3][jj3][o]
+  const int64_t N = v.nqtot;
+  const T* __restrict__ f = static_cast<const T*>(v.field) + l + plane * qs3;
+  T acc[IC * NCH];
+#pragma unroll
+  for (int k = 0; k < IC * NCH; ++k) acc[k] = T(0);
+#pragma unroll 2
+  for (int qq3 = 0; qq3 < qc3; ++qq3) {
+    const T* fk = f + plane * qq3;
+    const T* t = T3 + qq3 * IC * 4;   // uniform: scalar loads
+    if constexpr (STIFF) {
+      const T k11 = fk[1 * N], k22 = fk[2 * N], k33 = fk[3 * N];
+      const T k12 = fk[4 * N], k13 = fk[5 * N], k23 = fk[6 * N];
+#pragma unroll
+      for (int jj = 0; jj < IC; ++jj) {
+        const T t0 = t[jj * 4 + R00], t1 = t[jj * 4 + R10], t2 = t[jj * 4 + R01], t3 = t[jj * 4 + R11];
+        T* a = acc + jj * NCH;
+        a[0] += t0 * k11;
+        a[1] += t0 * k22;
+        a[2] += t3 * k33;
+        a[3] += t0 * k12;
+        a[4] += t1 * k13;
+        a[5] += t2 * k13;
+        a[6] += t1 * k23;
+        a[7] += t2 * k23;
+      }
+    } else {
+      const T k0 = fk[0];
+#pragma unroll
+      for (int jj = 0; jj < IC; ++jj) acc[jj] += t[jj * 4 + R00] * k0;
+    }
+  }
+  T* y = static_cast<T*>(v.ybuf) + (int64_t(i3) * plane + l) * (IC * NCH);
+  store_vec<T, IC * NCH>(y, acc);
+}
+
 template <int P, typename T, bool STIFF>
 __global__ __launch_bounds__((Shape<P, T, STIFF>::NT)) void k_push(PlanView v, T* __restrict__ out, int nseg) {
   using S = Shape<P, T, STIFF>;
@@ -136,9 +226,8 @@ __global__ __launch_bounds__((Shape<P, T, STIFF>::NT)) void k_push(PlanView v, T
   item /= n2;
   const int seg = item % nseg, i3 = item / nseg;
 
-  int qs2, qc2, qs3, qc3, is2, ic2, is3, ic3;
+  int qs2, qc2, is2, ic2, is3, ic3;
   q_range(i2, P, d2.nel, qs2, qc2);
-  q_range(i3, P, d3.nel, qs3, qc3);
   i_range(i2, P, n2, is2, ic2);
   i_range(i3, P, d3.n, is3, ic3);
   const int j3lo = part * J3;
@@ -151,9 +240,8 @@ __global__ __launch_bounds__((Shape<P, T, STIFF>::NT)) void k_push(PlanView v, T
   const int qbeg = e0 == 0 ? 0 : P + 2 * e0 - 1;        // knot chi_e0 opens span e0
   const int qend = e1 == nel1 - 1 ? nq1 : P + 2 * e1 + 1;
 
-  const int64_t N = v.nqtot;
-  const T* __restrict__ field = static_cast<const T*>(v.field);
-  const T* __restrict__ T3 = op_t<T>(d3) + size_t(i3) * QC * IC * 4;    // [qq3][jj3][o]
+  constexpr int NCH = S::NCH;
+  const T* __restrict__ Yb = static_cast<const T*>(v.ybuf) + int64_t(i3) * nq2 * nq1 * IC * NCH;   // [q2][q1][jj3][ch]
   const T* __restrict__ w2 = wt_t<T>(d2) + size_t(i2) * QC * 4;         // [qq2][o]
   const T* __restrict__ B2 = bt_t<T>(d2) + size_t(i2) * QC * IC * 2;    // [qq2][jj2][a]
   const T* __restrict__ CT = colt_t<T>(d1);                             // [q1][NCT]
@@ -199,90 +287,59 @@ __global__ __launch_bounds__((Shape<P, T, STIFF>::NT)) void k_push(PlanView v, T
     for (int d = 0; d <= 2 * P; ++d) acc[P][d] = T(0);
   };
 
-  int e_cur = e0;
-  for (int col0 = qbeg; col0 < qend; col0 += C) {
-    // ---------------- phase A ----------------
-    for (int it = tid; it < C * QC; it += NT) {
-      const int c = it % C, qq2 = it / C;
+  // dir-2 weights of row i2
+  __shared__ T w2s[QC * 4];
+  for (int t = tid; t < QC * 4; t += NT) w2s[t] = w2[t];
+
+  // Phase A input of a chunk: records (u, c, qq2) of the first contraction.
+  // Each lane holds RPL records in registers; the records of the next chunk
+  // are loaded while the current one goes through phases B and C.
+  constexpr int NREC = QC * C * J3, RPL = (NREC + NT - 1) / NT;
+  T pre[RPL][NCH];
+  auto fetch = [&](int col0) {
+#pragma unroll
+    for (int r = 0; r < RPL; ++r) {
+      const int it = tid + r * NT;
+      const int u = it % J3, c = (it / J3) % C, qq2 = it / (J3 * C);
       const int q1 = col0 + c;
-      if (q1 >= qend || qq2 >= qc2) continue;
-      const int q2 = qs2 + qq2;
-      T Y[S::NCH][J3];
+      if (it < NREC && q1 < qend && qq2 < qc2 && u < nj3)
+        load_vec<T, NCH>(Yb + ((int64_t(qs2 + qq2) * nq1 + q1) * IC + j3lo + u) * NCH, pre[r]);
+    }
+  };
+  // fold in the dir-2 weights and stage the merged arrays H in LDS
+  auto merge = [&](int col0) {
 #pragma unroll
-      for (int ch = 0; ch < S::NCH; ++ch)
-#pragma unroll
-        for (int u = 0; u < J3; ++u) Y[ch][u] = T(0);
-      const T* f = field + q1 + int64_t(nq1) * (q2 + int64_t(nq2) * qs3);
-      const int64_t fstride = int64_t(nq1) * nq2;
-      constexpr int KB = WQ_KB;
-      constexpr int NF = STIFF ? 6 : 1;
-#pragma unroll 1
-      for (int b0 = 0; b0 < QC; b0 += KB) {
-        if (b0 < qc3) {   // uniform
-          T kv[KB][NF];
-#pragma unroll
-          for (int kb = 0; kb < KB; ++kb) {
-            const int qq3 = b0 + kb;
-            if (qq3 < qc3) {
-              const T* fk = f + qq3 * fstride;
-#pragma unroll
-              for (int fi = 0; fi < NF; ++fi) kv[kb][fi] = fk[(STIFF ? fi + 1 : 0) * N];
-            } else {
-#pragma unroll
-              for (int fi = 0; fi < NF; ++fi) kv[kb][fi] = T(0);
-            }
-          }
-#pragma unroll
-          for (int kb = 0; kb < KB; ++kb) {
-            const int qq3 = b0 + kb;
-            if (qq3 < qc3) {   // uniform
-              const T* t = T3 + __builtin_amdgcn_readfirstlane((qq3 * IC + j3lo) * 4);
-              if constexpr (STIFF) {
-                const T k11 = kv[kb][0], k22 = kv[kb][1], k33 = kv[kb][2];
-                const T k12 = kv[kb][3], k13 = kv[kb][4], k23 = kv[kb][5];
-#pragma unroll
-                for (int u = 0; u < J3; ++u) {
-                  if (j3lo + u < IC) {   // uniform
-                    const T t0 = t[u * 4 + R00], t1 = t[u * 4 + R10], t2 = t[u * 4 + R01], t3 = t[u * 4 + R11];
-                    Y[0][u] += t0 * k11;
-                    Y[1][u] += t0 * k22;
-                    Y[2][u] += t3 * k33;
-                    Y[3][u] += t0 * k12;
-                    Y[4][u] += t1 * k13;
-                    Y[5][u] += t2 * k13;
-                    Y[6][u] += t1 * k23;
-                    Y[7][u] += t2 * k23;
-                  }
-                }
-              } else {
-#pragma unroll
-                for (int u = 0; u < J3; ++u)
-                  if (j3lo + u < IC) Y[0][u] += t[u * 4 + R00] * kv[kb][0];
-              }
-            }
-          }
-        }
-      }
-      // fold in the dir-2 weights of this q2 (weight merge)
-      T* h = hbuf + (size_t(c) * NH * QC + qq2) * J3;
+    for (int r = 0; r < RPL; ++r) {
+      const int it = tid + r * NT;
+      const int u = it % J3, c = (it / J3) % C, qq2 = it / (J3 * C);
+      const int q1 = col0 + c;
+      if (!(it < NREC && q1 < qend && qq2 < qc2 && u < nj3)) continue;
+      const T* Y = pre[r];
+      const T* a = w2s + qq2 * 4;
+      T* h = hbuf + (size_t(c) * NH * QC + qq2) * J3 + u;
       if constexpr (STIFF) {
-        const T* a = w2 + qq2 * 4;
-        const T a0 = a[R00], a1 = a[R10], a2 = a[R01], a3 = a[R11];
-#pragma unroll
-        for (int u = 0; u < J3; ++u) {
-          h[0 * QC * J3 + u] = a3 * Y[1][u] + a1 * Y[7][u];   // -> G_(0,0) through B2^(1)
-          h[1 * QC * J3 + u] = a0 * Y[2][u] + a2 * Y[6][u];   // -> G_(0,0) through B2^(0)
-          h[2 * QC * J3 + u] = a0 * Y[0][u];                  // -> G_(1,1) through B2^(0)
-          h[3 * QC * J3 + u] = a1 * Y[3][u];                  // -> G_(0,1) through B2^(1)
-          h[4 * QC * J3 + u] = a0 * Y[4][u];                  // -> G_(0,1) through B2^(0)
-          h[5 * QC * J3 + u] = a2 * Y[3][u] + a0 * Y[5][u];   // -> G_(1,0) through B2^(0)
-        }
+        h[0 * QC * J3] = a[R11] * Y[1] + a[R10] * Y[7];   // -> G_(0,0) through B2^(1)
+        h[1 * QC * J3] = a[R00] * Y[2] + a[R01] * Y[6];   // -> G_(0,0) through B2^(0)
+        h[2 * QC * J3] = a[R00] * Y[0];                   // -> G_(1,1) through B2^(0)
+        h[3 * QC * J3] = a[R10] * Y[3];                   // -> G_(0,1) through B2^(1)
+        h[4 * QC * J3] = a[R00] * Y[4];                   // -> G_(0,1) through B2^(0)
+        h[5 * QC * J3] = a[R01] * Y[3] + a[R00] * Y[5];   // -> G_(1,0) through B2^(0)
       } else {
-        const T a0 = w2[qq2 * 4 + R00];
-#pragma unroll
-        for (int u = 0; u < J3; ++u) h[u] = a0 * Y[0][u];
+        h[0] = a[R00] * Y[0];
       }
     }
+  };
+
+  if constexpr (STIFF)   // the zero array H_6
+    for (int t = tid; t < C * QC * J3; t += NT) hbuf[(size_t(t / (QC * J3)) * NH + 6) * QC * J3 + t % (QC * J3)] = T(0);
+
+  int e_cur = e0;
+  fetch(qbeg);
+  __syncthreads();
+  for (int col0 = qbeg; col0 < qend; col0 += C) {
+    // ---------------- phase A ----------------
+    merge(col0);
+    if (col0 + C < qend) fetch(col0 + C);
     __syncthreads();
     // ---------------- phase B ----------------
     // item (u, c, g); group g: 0 = G_(0,0), 1 = G_(1,0), 2 = G_(0,1), 3 = G_(1,1)
@@ -290,9 +347,9 @@ __global__ __launch_bounds__((Shape<P, T, STIFF>::NT)) void k_push(PlanView v, T
       const int u = it % J3, c = (it / J3) % C, g = it / (J3 * C);
       const int q1 = col0 + c;
       if (q1 >= qend || u >= nj3) continue;
-      int h1, h0;   // inputs through B2^(1) and B2^(0); -1 = none
+      int h1, h0;   // inputs through B2^(1) and B2^(0)
       if constexpr (STIFF) {
-        h1 = g == 0 ? 0 : (g == 2 ? 3 : -1);
+        h1 = g == 0 ? 0 : (g == 2 ? 3 : 6);   // 6: the zero array
         h0 = g == 0 ? 1 : (g == 1 ? 5 : (g == 2 ? 4 : 2));
       } else {
         h1 = -1;
@@ -306,12 +363,12 @@ __global__ __launch_bounds__((Shape<P, T, STIFF>::NT)) void k_push(PlanView v, T
       for (int qq2 = 0; qq2 < QC; ++qq2) {
         if (qq2 < qc2) {   // uniform
           const T x0 = hb[(h0 * QC + qq2) * J3];
-          const T x1 = h1 >= 0 ? hb[(h1 * QC + qq2) * J3] : T(0);
+          const T x1 = STIFF ? hb[(h1 * QC + qq2) * J3] : T(0);
           const T* b = B2 + __builtin_amdgcn_readfirstlane(qq2 * IC * 2);
 #pragma unroll
           for (int jj2 = 0; jj2 < IC; ++jj2) {
-            if constexpr (STIFF) G[jj2] += b[jj2 * 2] * x0 + b[jj2 * 2 + 1] * x1;
-            else G[jj2] += b[jj2 * 2] * x0;
+            if constexpr (STIFF) G[jj2] = fma(b[jj2 * 2 + 1], x1, fma(b[jj2 * 2], x0, G[jj2]));
+            else G[jj2] = fma(b[jj2 * 2], x0, G[jj2]);
           }
         }
       }
@@ -341,7 +398,7 @@ __global__ __launch_bounds__((Shape<P, T, STIFF>::NT)) void k_push(PlanView v, T
             const T H1 = w[R10] * g10 + w[R11] * g11;
 #pragma unroll
             for (int r = 0; r <= P; ++r)
-              acc[s][r - s + P] += ct[4 * (P + 1) + r] * H0 + ct[5 * (P + 1) + r] * H1;
+              acc[s][r - s + P] = fma(ct[5 * (P + 1) + r], H1, fma(ct[4 * (P + 1) + r], H0, acc[s][r - s + P]));
           }
         } else {
           const T g0 = gb[0];
@@ -349,7 +406,7 @@ __global__ __launch_bounds__((Shape<P, T, STIFF>::NT)) void k_push(PlanView v, T
           for (int s = 0; s <= P; ++s) {
             const T H0 = ct[s * 4 + R00] * g0;
 #pragma unroll
-            for (int r = 0; r <= P; ++r) acc[s][r - s + P] += ct[4 * (P + 1) + r] * H0;
+            for (int r = 0; r <= P; ++r) acc[s][r - s + P] = fma(ct[4 * (P + 1) + r], H0, acc[s][r - s + P]);
           }
         }
       }
@@ -369,6 +426,8 @@ hipError_t push_launch(const PlanView& v, void* out, hipStream_t s) {
   const int nseg = int(std::min<int64_t>(max_seg, std::max<int64_t>(1, (WQ_WG_TARGET + wgs - 1) / wgs)));
   const int64_t items = wgs * nseg;
   if (items <= 0 || items > INT32_MAX) return hipErrorInvalidConfiguration;
+  const int64_t plane = int64_t(v.dir[0].nq) * v.dir[1].nq;
+  hipLaunchKernelGGL((k_first<P, T, STIFF>), dim3(unsigned((plane + 255) / 256), unsigned(v.dir[2].n)), dim3(256), 0, s, v);
   hipLaunchKernelGGL((k_push<P, T, STIFF>), dim3(unsigned(items)), dim3(Sh::NT), 0, s, v, static_cast<T*>(out), nseg);
   return hipGetLastError();
 }

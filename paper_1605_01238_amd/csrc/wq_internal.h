@@ -24,6 +24,7 @@
 namespace wq {
 
 constexpr int kNumChannels = 7;   // det J, K11, K22, K33, K12, K13, K23
+constexpr int kYChannels = 8;     // distinct (coefficient, dir-3 rule) pairs of the stiffness
 constexpr int kNumFlags = 16;
 
 // Latched device conditions (int32 counters in the workspace).
@@ -89,6 +90,7 @@ struct PlanView {
   int prec;
   DirView dir[3];
   void* field;           // kNumChannels * nqtot in the plan precision
+  void* ybuf;            // [n3][nq2][nq1][icap][kYChannels]: field contracted over q3 per test index i3
   double* ctrl;          // n3*n2*n1*3
   double* dctrl;         // 3 * n3*n2*n1*3: C_i - C_{i - e_b} along direction b (0 where i_b = 0)
   int32_t* flags;        // kNumFlags
@@ -97,7 +99,7 @@ struct PlanView {
 
 struct Layout {
   size_t knots[3], x[3], qspan[3], bv[3], bd[3], bw[3], w[3], op64[3], op32[3], bt64[3], bt32[3], wt64[3], wt32[3], prefix[3], colt64[3], colt32[3];
-  size_t field, ctrl, dctrl, flags, total;
+  size_t field, ybuf, ctrl, dctrl, flags, total;
 };
 
 }  // namespace wq

@@ -66,7 +66,10 @@ void compute_layout(wq_plan* pl) {
     L.colt64[k] = take(nq * 6 * (p + 1) * 8);
     L.colt32[k] = take(nq * 6 * (p + 1) * 4);
   }
-  L.field = take(size_t(wq::kNumChannels) * size_t(pl->nqtot) * (pl->prec == WQ_FP64 ? 8 : 4));
+  const size_t elem = pl->prec == WQ_FP64 ? 8 : 4;
+  L.field = take(size_t(wq::kNumChannels) * size_t(pl->nqtot) * elem);
+  // first contraction (over q3) of the coefficient field: [n3][nq2][nq1][icap][8]
+  L.ybuf = take(size_t(pl->n[2]) * size_t(pl->nq[1]) * size_t(pl->nq[0]) * ic * wq::kYChannels * elem);
   L.ctrl = take(size_t(pl->nrows) * 3 * 8);
   L.dctrl = take(size_t(pl->nrows) * 9 * 8);
   L.flags = take(wq::kNumFlags * 4);
@@ -102,6 +105,7 @@ wq::PlanView wq_plan::view() const {
     d.colt32 = reinterpret_cast<float*>(ws + lay.colt32[k]);
   }
   v.field = ws + lay.field;
+  v.ybuf = ws + lay.ybuf;
   v.ctrl = reinterpret_cast<double*>(ws + lay.ctrl);
   v.dctrl = reinterpret_cast<double*>(ws + lay.dctrl);
   v.flags = reinterpret_cast<int32_t*>(ws + lay.flags);
