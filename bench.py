@@ -41,7 +41,9 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
                     help="approximate CPU budget of the oracle baseline (0 disables)")
     ap.add_argument("--traffic-json", default=os.path.join(ROOT, "profiles", "traffic.json"),
-                    help="measured HBM bytes per contraction launch (from rocprofv3 --pmc)")
+                    help="measured HBM bytes per wq_assemble (rocprofv3 --pmc FETCH_SIZE and "
+                         "WRITE_SIZE, scaled by a plain copy); ignored once the contraction "
+                         "source has changed since the counters were taken")
     return ap.parse_args()
 
 
@@ -68,6 +70,24 @@ def cpu_baseline(w, which_names, budget_s):
             "sample": f"{rows} random rows of the same workload ({'+'.join(which_names)}), "
                       f"sum-factorized FP64 oracle rows incl. per-row geometry, {dt:.1f} s; "
                       f"one-time exact-rational rule setup {t_rules:.1f} s not included"}
+
+
+def contraction_source_digest():
+    import hashlib
+    src = os.path.join(ROOT, "paper_1605_01238_amd", "csrc", "wq_contract.hip")
+    return hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+
+
+def measured_traffic(path, key):
+    """HBM bytes per wq_assemble from the committed counter summary, or None
+    when there is none for this workload or the kernels changed since."""
+    try:
+        entry = json.load(open(path)).get(key)
+    except (OSError, ValueError):
+        return None
+    if not entry or entry.get("source_digest") != contraction_source_digest():
+        return None
+    return entry.get("bytes_per_launch")
 
 
 def main():
@@ -104,16 +124,18 @@ def main():
     mass = torch.empty(plan.nnz, dtype=plan.value_dtype, device="cuda") if which & 1 else None
     stiff = torch.empty(plan.nnz, dtype=plan.value_dtype, device="cuda") if which & 2 else None
     stream = torch.cuda.current_stream()
-    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2 * args.steps)]
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(3 * args.steps)]
 
     def step(i=None):
+        if i is not None:
+            ev[3 * i].record(stream)
         plan.setup(ctrl, coef)
         plan.pattern(row_ptr, col_idx)
         if i is not None:
-            ev[2 * i].record(stream)
+            ev[3 * i + 1].record(stream)
         plan.assemble(which, mass, stiff)
         if i is not None:
-            ev[2 * i + 1].record(stream)
+            ev[3 * i + 2].record(stream)
 
     for _ in range(args.warmup):
         step()
@@ -129,21 +151,16 @@ def main():
     n_mat = len(which_names)
     ms_per_step = dt / args.steps * 1e3
     value = plan.nnz * n_mat / (dt / args.steps) / 1e9
-    t_asm = np.array([ev[2 * i].elapsed_time(ev[2 * i + 1]) for i in range(args.steps)])  # ms
+    t_asm = np.array([ev[3 * i + 1].elapsed_time(ev[3 * i + 2]) for i in range(args.steps)])  # ms
+    t_step = np.array([ev[3 * i].elapsed_time(ev[3 * i + 2]) for i in range(args.steps)])    # ms
     # algorithmic bytes of one contraction launch: the values written plus one
     # read of the coefficient-field channels it uses
     chans = (6 if which & 2 else 0) + (1 if which & 1 else 0)
     algo_bytes = plan.nnz * bv * n_mat + plan.n_qp_total * chans * bv
     achieved = algo_bytes / (t_asm.mean() * 1e-3) / 1e9
-    traffic = None
-    key = f"{w.name}:{args.precision}:{'+'.join(which_names)}"
-    if os.path.exists(args.traffic_json):
-        try:
-            traffic = json.load(open(args.traffic_json)).get(key)
-        except (ValueError, OSError):
-            traffic = None
+    traffic = measured_traffic(args.traffic_json, f"{w.name}:{args.precision}:{'+'.join(which_names)}")
     out = {
-        "metric": "assembled nonzeros/s (GNNZ/s) + % HBM-write roofline, 3D p=4..6",
+        "metric": "assembled nonzeros/s (GNNZ/s) + % HBM-write roofline, 3D p=4..6; p99 latency",
         "value": round(value, 4),
         "unit": "GNNZ/s",
         "n_gpus": 1,
@@ -158,11 +175,15 @@ def main():
         "config": {"workload": w.name, "p": w.p, "n_el": list(w.n_el), "matrices": list(which_names),
                    "nnz_per_matrix": plan.nnz, "n_dof": plan.n_rows, "n_qp": plan.n_qp_total,
                    "step": "wq_setup + wq_pattern + wq_assemble", "parallelism": "single GPU"},
-        "roofline": {"bound": "hbm", "kernel": "contraction (wq_assemble)",
+        "roofline": {"bound": "hbm", "kernel": "wq_assemble = k_first + k_push (two launches)",
                      "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                      "launch_ms_mean": round(float(t_asm.mean()), 4),
                      "algorithmic_bytes_per_launch": int(algo_bytes)},
+        "latency_ms": {"step_p50": round(float(np.percentile(t_step, 50)), 4),
+                       "step_p99": round(float(np.percentile(t_step, 99)), 4),
+                       "assemble_p50": round(float(np.percentile(t_asm, 50)), 4),
+                       "assemble_p99": round(float(np.percentile(t_asm, 99)), 4)},
     }
     if args.cpu_seconds > 0:
         out["cpu_baseline"] = cpu_baseline(w, which_names, args.cpu_seconds)

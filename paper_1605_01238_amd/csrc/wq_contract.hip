@@ -46,7 +46,7 @@
 // Pencils are split into runs of rows until the grid holds about this many
 // workgroups.
 #ifndef WQ_WG_TARGET
-#define WQ_WG_TARGET 2048
+#define WQ_WG_TARGET 4096
 #endif
 
 namespace wq {
@@ -76,7 +76,7 @@ struct Shape {
   static constexpr int NT = 64 * Cfg::NW, J3 = Cfg::J3, C = Cfg::C;
   static constexpr int NPART = (IC + J3 - 1) / J3;        // j3 parts
   static constexpr int NG = STIFF ? 4 : 1;                // dir-1 rule groups
-  static constexpr int NH = STIFF ? 7 : 1;                // merged dir-2 inputs (+1 zero array)
+  static constexpr int NH = STIFF ? 6 : 1;                // merged dir-2 inputs
   static constexpr int NCH = STIFF ? 8 : 1;               // dir-3 channels
   static constexpr int NCT = 6 * (P + 1);                 // column-table entries
   static constexpr size_t HBUF = size_t(C) * NH * QC * J3;
@@ -279,12 +279,16 @@ __global__ __launch_bounds__((Shape<P, T, STIFF>::NT)) void k_push(PlanView v, T
       for (int t = tid; t < len; t += NT) o[t] = stage[t];
       __syncthreads();
     }
+    // the row in slot s has met the spans up to e only, whose trial
+    // functions end at e+P: offsets d <= 2P - s; only that part moves
 #pragma unroll
-    for (int s = 0; s < P; ++s)
+    for (int s = 0; s < P; ++s) {
 #pragma unroll
-      for (int d = 0; d <= 2 * P; ++d) acc[s][d] = acc[s + 1][d];
+      for (int d = 0; d < 2 * P - s; ++d) acc[s][d] = acc[s + 1][d];
+      acc[s][2 * P - s] = T(0);
+    }
 #pragma unroll
-    for (int d = 0; d <= 2 * P; ++d) acc[P][d] = T(0);
+    for (int d = 0; d <= P; ++d) acc[P][d] = T(0);
   };
 
   // dir-2 weights of row i2
@@ -296,14 +300,24 @@ __global__ __launch_bounds__((Shape<P, T, STIFF>::NT)) void k_push(PlanView v, T
   // are loaded while the current one goes through phases B and C.
   constexpr int NREC = QC * C * J3, RPL = (NREC + NT - 1) / NT;
   T pre[RPL][NCH];
+  // per record slot: offset in the slab for column 0 (records of absent
+  // items point at the slab start, so that every lane always loads)
+  uint32_t roff[RPL];
+#pragma unroll
+  for (int r = 0; r < RPL; ++r) {
+    const int it = tid + r * NT;
+    const int u = it % J3, c = (it / J3) % C, qq2 = it / (J3 * C);
+    roff[r] = (it < NREC && qq2 < qc2 && u < nj3) ? uint32_t(((qs2 + qq2) * nq1 + c) * IC + j3lo + u) * NCH : ~0u;
+  }
+  auto rec_valid = [&](int r, int col0) {
+    const int c = ((tid + r * NT) / J3) % C;
+    return roff[r] != ~0u && col0 + c < qend;
+  };
   auto fetch = [&](int col0) {
 #pragma unroll
     for (int r = 0; r < RPL; ++r) {
-      const int it = tid + r * NT;
-      const int u = it % J3, c = (it / J3) % C, qq2 = it / (J3 * C);
-      const int q1 = col0 + c;
-      if (it < NREC && q1 < qend && qq2 < qc2 && u < nj3)
-        load_vec<T, NCH>(Yb + ((int64_t(qs2 + qq2) * nq1 + q1) * IC + j3lo + u) * NCH, pre[r]);
+      const uint32_t off = rec_valid(r, col0) ? roff[r] + uint32_t(col0 * IC * NCH) : 0u;
+      load_vec<T, NCH>(Yb + off, pre[r]);
     }
   };
   // fold in the dir-2 weights and stage the merged arrays H in LDS
@@ -312,8 +326,7 @@ __global__ __launch_bounds__((Shape<P, T, STIFF>::NT)) void k_push(PlanView v, T
     for (int r = 0; r < RPL; ++r) {
       const int it = tid + r * NT;
       const int u = it % J3, c = (it / J3) % C, qq2 = it / (J3 * C);
-      const int q1 = col0 + c;
-      if (!(it < NREC && q1 < qend && qq2 < qc2 && u < nj3)) continue;
+      if (!rec_valid(r, col0)) continue;
       const T* Y = pre[r];
       const T* a = w2s + qq2 * 4;
       T* h = hbuf + (size_t(c) * NH * QC + qq2) * J3 + u;
@@ -330,8 +343,8 @@ __global__ __launch_bounds__((Shape<P, T, STIFF>::NT)) void k_push(PlanView v, T
     }
   };
 
-  if constexpr (STIFF)   // the zero array H_6
-    for (int t = tid; t < C * QC * J3; t += NT) hbuf[(size_t(t / (QC * J3)) * NH + 6) * QC * J3 + t % (QC * J3)] = T(0);
+  __shared__ T hzero[STIFF ? QC * J3 : 1];   // stands in for a missing B2^(1) input
+  for (int t = tid; t < (STIFF ? QC * J3 : 1); t += NT) hzero[t] = T(0);
 
   int e_cur = e0;
   fetch(qbeg);
@@ -349,7 +362,7 @@ __global__ __launch_bounds__((Shape<P, T, STIFF>::NT)) void k_push(PlanView v, T
       if (q1 >= qend || u >= nj3) continue;
       int h1, h0;   // inputs through B2^(1) and B2^(0)
       if constexpr (STIFF) {
-        h1 = g == 0 ? 0 : (g == 2 ? 3 : 6);   // 6: the zero array
+        h1 = g == 0 ? 0 : (g == 2 ? 3 : -1);   // -1: none (zeros)
         h0 = g == 0 ? 1 : (g == 1 ? 5 : (g == 2 ? 4 : 2));
       } else {
         h1 = -1;
@@ -358,18 +371,17 @@ __global__ __launch_bounds__((Shape<P, T, STIFF>::NT)) void k_push(PlanView v, T
       T G[IC];
 #pragma unroll
       for (int jj2 = 0; jj2 < IC; ++jj2) G[jj2] = T(0);
-      const T* hb = hbuf + size_t(c) * NH * QC * J3 + u;
-#pragma unroll 4
-      for (int qq2 = 0; qq2 < QC; ++qq2) {
-        if (qq2 < qc2) {   // uniform
-          const T x0 = hb[(h0 * QC + qq2) * J3];
-          const T x1 = STIFF ? hb[(h1 * QC + qq2) * J3] : T(0);
-          const T* b = B2 + __builtin_amdgcn_readfirstlane(qq2 * IC * 2);
+      const T* hb0 = hbuf + (size_t(c) * NH + h0) * QC * J3 + u;
+      const T* hb1 = h1 >= 0 ? hbuf + (size_t(c) * NH + h1) * QC * J3 + u : hzero + u;
+#pragma unroll 2
+      for (int qq2 = 0; qq2 < qc2; ++qq2) {   // uniform trip count
+        const T x0 = hb0[qq2 * J3];
+        const T x1 = STIFF ? hb1[qq2 * J3] : T(0);
+        const T* b = B2 + __builtin_amdgcn_readfirstlane(qq2 * IC * 2);
 #pragma unroll
-          for (int jj2 = 0; jj2 < IC; ++jj2) {
-            if constexpr (STIFF) G[jj2] = fma(b[jj2 * 2 + 1], x1, fma(b[jj2 * 2], x0, G[jj2]));
-            else G[jj2] = fma(b[jj2 * 2], x0, G[jj2]);
-          }
+        for (int jj2 = 0; jj2 < IC; ++jj2) {
+          if constexpr (STIFF) G[jj2] = fma(b[jj2 * 2 + 1], x1, fma(b[jj2 * 2], x0, G[jj2]));
+          else G[jj2] = fma(b[jj2 * 2], x0, G[jj2]);
         }
       }
       T* gb = gbuf + (size_t(c * NG + g) * IC) * J3 + u;

@@ -15,6 +15,16 @@ pytestmark = pytest.mark.gpu
 
 FP64_TOL = 1e-12
 FP32_TOL = 1e-5
+U32 = 2.0 ** -24
+
+
+def s1_tol(precision, p):
+    """Bound on max_i |sum_j s_ij| / sum_j |s_ij| (exactly 0 in exact
+    arithmetic).  FP64: 1e-13.  FP32: the row sum adds up (2p+1)^3 entries
+    whose rounding errors are independent, each below ~16 units of FP32
+    roundoff relative to the row's absolute sum: a random walk gives
+    16 u32 sqrt((2p+1)^3)."""
+    return 1e-13 if precision == 0 else 16 * U32 * ((2 * p + 1) ** 3) ** 0.5
 
 
 def check_structure(plan, row_ptr, col_idx, rows, problem):
@@ -88,10 +98,9 @@ def test_mid_p4_stiffness(mid_oracle, precision):
     assert not bool(torch.isnan(stiff).any())
     if precision == 0:
         assert row_err <= FP64_TOL
-        assert s1 <= 1e-13
     else:
         assert mat_err <= FP32_TOL
-        assert s1 <= 1e-5
+    assert s1 <= s1_tol(precision, w.p)
     del stiff, col_idx, row_ptr, plan
     torch.cuda.empty_cache()
 
@@ -137,7 +146,7 @@ def test_large_p6_mass_and_stiffness(large_oracle, precision):
             assert mat_err <= FP32_TOL
     s1 = stiffness_kills_constants(row_ptr, stiff)
     print(f"[p6 64^3 prec={precision}] max|S1|/sum|S| {s1:.2e}")
-    assert s1 <= (1e-13 if precision == 0 else 1e-5)
+    assert s1 <= s1_tol(precision, w.p)
     # total mass ~ volume of the mapped domain (not exact for a non-affine map)
     tot = float(mass.double().sum())
     print(f"[p6 64^3 prec={precision}] total mass {tot:.12f}")
