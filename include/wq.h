@@ -36,7 +36,8 @@
  *
  * Memory and streams: the library never allocates device memory.  The
  * caller allocates one workspace (size from wq_sizes) and all outputs, and
- * owns them.  Device calls are asynchronous on the given HIP stream
+ * owns them.  A bound plan owns one HIP stream and two events of its own
+ * (see wq_setup), released by wq_plan_destroy.  Device calls are asynchronous on the given HIP stream
  * (0 = the legacy default stream).  Host pointers are read before the call
  * returns.  A plan is a host object; it is not thread-safe; distinct plans
  * are independent.
@@ -138,6 +139,11 @@ wq_status wq_bind(wq_plan* plan, void* workspace, size_t bytes, hipStream_t stre
  *   coef_dev  device FP64 array of the diffusion coefficient a at the
  *             quadrature points, [n_qp3][n_qp2][n_qp1] (q1 fastest), or NULL
  *             for a = 1.  Read during this call only.
+ * Ordering: stage 1 runs on a stream owned by the plan, after all work
+ * already queued on `stream`; wq_assemble, wq_weights and wq_sync wait for
+ * it (on their own stream), so results are as if everything ran on
+ * `stream`, while wq_pattern, wq_field and wq_set_coefficient, which do not
+ * read its tables, may overlap it.
  * Errors: WQ_EINVAL, WQ_ESTATE, WQ_EDEVICE; det J <= 0 and solve breakdowns
  * are latched for wq_sync.
  */

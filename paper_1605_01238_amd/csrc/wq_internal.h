@@ -114,13 +114,20 @@ struct wq_plan {
   size_t ws_bytes = 0;
   bool bound = false, setup_done = false;
   std::string err;
+  // The univariate stage runs on a second stream, forked from the caller's
+  // stream at wq_setup and joined by the calls that read its tables.
+  hipStream_t aux = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_rules = nullptr;
+  bool rules_launched = false;
   wq::PlanView view() const;
+  ~wq_plan();
 };
 
 namespace wq {
 // Kernel launchers (return hipError_t of the launch).
 hipError_t launch_points(const PlanView& v, hipStream_t s);
 hipError_t launch_rules(const PlanView& v, hipStream_t s);
+hipError_t launch_prefix(const PlanView& v, hipStream_t s);
 hipError_t launch_ctrl_diff(const PlanView& v, hipStream_t s);
 hipError_t launch_coltab(const PlanView& v, hipStream_t s);
 hipError_t launch_geometry(const PlanView& v, const double* coef, double* xphys_out, hipStream_t s);

@@ -68,8 +68,12 @@ void compute_layout(wq_plan* pl) {
   }
   const size_t elem = pl->prec == WQ_FP64 ? 8 : 4;
   L.field = take(size_t(wq::kNumChannels) * size_t(pl->nqtot) * elem);
-  // first contraction (over q3) of the coefficient field: [n3][nq2][nq1][icap][8]
-  L.ybuf = take(size_t(pl->n[2]) * size_t(pl->nq[1]) * size_t(pl->nq[0]) * ic * wq::kYChannels * elem);
+  // first contraction (over q3) of the coefficient field: [n3][nq2][nq1][icap][8];
+  // before an assembly it also holds the geometry pass intermediates
+  // ([nq3][n2][n1][9] and [nq3][nq2][n1][9] doubles)
+  const size_t ybytes = size_t(pl->n[2]) * size_t(pl->nq[1]) * size_t(pl->nq[0]) * ic * wq::kYChannels * elem;
+  const size_t gbytes = size_t(pl->nq[2]) * size_t(pl->n[0]) * (size_t(pl->n[1]) + size_t(pl->nq[1])) * 9 * 8;
+  L.ybuf = take(ybytes > gbytes ? ybytes : gbytes);
   L.ctrl = take(size_t(pl->nrows) * 3 * 8);
   L.dctrl = take(size_t(pl->nrows) * 9 * 8);
   L.flags = take(wq::kNumFlags * 4);
@@ -77,6 +81,15 @@ void compute_layout(wq_plan* pl) {
 }
 
 }  // namespace
+
+wq_plan::~wq_plan() {
+  if (aux) {
+    (void)hipStreamSynchronize(aux);
+    (void)hipStreamDestroy(aux);
+  }
+  if (ev_fork) (void)hipEventDestroy(ev_fork);
+  if (ev_rules) (void)hipEventDestroy(ev_rules);
+}
 
 wq::PlanView wq_plan::view() const {
   wq::PlanView v{};
@@ -209,9 +222,22 @@ wq_status wq_bind(wq_plan* plan, void* workspace, size_t bytes, hipStream_t stre
     e = hipMemcpyAsync(plan->ws + plan->lay.flags + 4 * wq::FLAG_SOLVE_FIRST, &init[1], 4, hipMemcpyHostToDevice, stream);
   if (e != hipSuccess) return hip_fail(plan, e, "wq_bind: flag init");
   e = wq::launch_points(plan->view(), stream);
+  if (e == hipSuccess) e = wq::launch_prefix(plan->view(), stream);
   if (e != hipSuccess) return hip_fail(plan, e, "wq_bind: points kernel");
+  if (!plan->aux) {
+    e = hipStreamCreateWithFlags(&plan->aux, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&plan->ev_fork, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&plan->ev_rules, hipEventDisableTiming);
+    if (e != hipSuccess) return hip_fail(plan, e, "wq_bind: stream/event creation");
+  }
+  plan->rules_launched = false;
   plan->err.clear();
   return WQ_OK;
+}
+
+// Make `stream` wait for the univariate stage of the last wq_setup.
+static hipError_t join_rules(const wq_plan* plan, hipStream_t stream) {
+  return plan->rules_launched ? hipStreamWaitEvent(stream, plan->ev_rules, 0) : hipSuccess;
 }
 
 wq_status wq_setup(wq_plan* plan, const double* ctrl_dev, const double* coef_dev, hipStream_t stream) {
@@ -222,12 +248,17 @@ wq_status wq_setup(wq_plan* plan, const double* ctrl_dev, const double* coef_dev
                                 hipMemcpyDeviceToDevice, stream);
   if (e != hipSuccess) return hip_fail(plan, e, "wq_setup: control net copy");
   wq::PlanView v = plan->view();
+  // univariate stage on the second stream, after everything already queued
+  // on `stream` (earlier assemblies read the tables it rewrites)
+  e = hipEventRecord(plan->ev_fork, stream);
+  if (e == hipSuccess) e = hipStreamWaitEvent(plan->aux, plan->ev_fork, 0);
+  if (e == hipSuccess) e = wq::launch_rules(v, plan->aux);
+  if (e == hipSuccess) e = wq::launch_coltab(v, plan->aux);
+  if (e == hipSuccess) e = hipEventRecord(plan->ev_rules, plan->aux);
+  if (e != hipSuccess) return hip_fail(plan, e, "wq_setup: univariate kernel");
+  plan->rules_launched = true;
   e = wq::launch_ctrl_diff(v, stream);
   if (e != hipSuccess) return hip_fail(plan, e, "wq_setup: control-net differences");
-  e = wq::launch_rules(v, stream);
-  if (e != hipSuccess) return hip_fail(plan, e, "wq_setup: univariate kernel");
-  e = wq::launch_coltab(v, stream);
-  if (e != hipSuccess) return hip_fail(plan, e, "wq_setup: column tables");
   e = wq::launch_geometry(v, coef_dev, nullptr, stream);
   if (e != hipSuccess) return hip_fail(plan, e, "wq_setup: geometry kernel");
   plan->setup_done = true;
@@ -262,7 +293,9 @@ wq_status wq_assemble(wq_plan* plan, int which, void* mass, void* stiff, hipStre
   if ((which & WQ_MASS) && !mass) return fail(plan, WQ_EINVAL, "null mass output");
   if ((which & WQ_STIFF) && !stiff) return fail(plan, WQ_EINVAL, "null stiffness output");
   if (!plan->setup_done) return fail(plan, WQ_ESTATE, "wq_assemble before wq_setup");
-  hipError_t e = wq::launch_assemble(plan->view(), which, mass, stiff, stream);
+  hipError_t e = join_rules(plan, stream);
+  if (e != hipSuccess) return hip_fail(plan, e, "wq_assemble: join");
+  e = wq::launch_assemble(plan->view(), which, mass, stiff, stream);
   if (e != hipSuccess) return hip_fail(plan, e, "wq_assemble: contraction kernel");
   return WQ_OK;
 }
@@ -273,8 +306,10 @@ wq_status wq_weights(const wq_plan* plan, int dir, int pair, double* w_dev, int3
   if (!plan->setup_done) return WQ_ESTATE;
   const int p = plan->p, n = int(plan->n[dir]), qc = wq::qcap_of(p);
   const size_t bytes = size_t(n) * qc * 8;
-  hipError_t e = hipMemcpyAsync(w_dev, plan->ws + plan->lay.w[dir] + size_t(pair) * bytes, bytes,
-                                hipMemcpyDeviceToDevice, stream);
+  hipError_t e = join_rules(plan, stream);
+  if (e != hipSuccess) return WQ_EDEVICE;
+  e = hipMemcpyAsync(w_dev, plan->ws + plan->lay.w[dir] + size_t(pair) * bytes, bytes,
+                     hipMemcpyDeviceToDevice, stream);
   if (e != hipSuccess) return WQ_EDEVICE;
   if (qs_dev || qc_dev) {
     std::vector<int32_t> s(n), c(n);
@@ -302,6 +337,7 @@ wq_status wq_field(const wq_plan* plan, void* field_dev, hipStream_t stream) {
 wq_status wq_sync(wq_plan* plan, hipStream_t stream) {
   if (!plan) return WQ_EINVAL;
   hipError_t e = hipStreamSynchronize(stream);
+  if (e == hipSuccess && plan->rules_launched) e = hipEventSynchronize(plan->ev_rules);
   if (e != hipSuccess) return hip_fail(plan, e, "wq_sync");
   if (!plan->bound) return WQ_OK;
   int32_t f[wq::kNumFlags];

@@ -77,6 +77,12 @@ __device__ inline dd qp_coord(const double* __restrict__ k, int P, int nel, int 
   return dd{0.5 * s.hi, 0.5 * s.lo};
 }
 
+__device__ inline double wave_max(double x) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) x = fmax(x, __shfl_xor(x, off, 64));
+  return x;
+}
+
 __device__ inline double wave_sum(double x) {
 #pragma unroll
   for (int off = 32; off >= 1; off >>= 1) x += __shfl_xor(x, off, 64);
@@ -141,9 +147,15 @@ __global__ __launch_bounds__(256) void k_ctrl_diff(PlanView v) {
 // at p = 6), so their data -- points, B-spline values, Gauss nodes/weights
 // and integrals -- are formed in double-double.  The minimum-norm problem is
 // the KKT system  w - A^T lam = 0,  A w = b;  it is solved with a Householder
-// QR of A^T (lane = quadrature point = row of A^T) in FP64 and refined twice
-// with residuals evaluated in double-double, which yields the weights to
-// FP64 rounding.
+// QR of A^T (lane = quadrature point = row of A^T) in FP64 and refined
+// with residuals evaluated in double-double (at least once, at most three
+// times, until a step no longer matters), which yields the weights to FP64
+// rounding.
+// KKT steps of the minimum-norm solve at most (the first is the plain solve).
+#ifndef WQ_KKT_ITERS
+#define WQ_KKT_ITERS 4
+#endif
+
 template <int P>
 __global__ __launch_bounds__(256) void k_rules(PlanView v) {
   constexpr int QC = 3 * P + 1, IC = 2 * P + 1, NG = P + 1, MAXG = (P + 1) * NG;
@@ -299,7 +311,7 @@ __global__ __launch_bounds__(256) void k_rules(PlanView v) {
   dd lam[IC];
 #pragma unroll
   for (int j = 0; j < IC; ++j) lam[j] = dd{0.0, 0.0};
-  for (int it = 0; it < 3 && !broke; ++it) {
+  for (int it = 0; it < WQ_KKT_ITERS && !broke; ++it) {
     // r2 = b - A w (kept equations), r1 = A^T lam - w (this lane)
     double r2[IC];
     dd r1 = -w;
@@ -357,6 +369,14 @@ __global__ __launch_bounds__(256) void k_rules(PlanView v) {
 #pragma unroll
     for (int j = 0; j < IC; ++j)
       if (j < r) lam[j] = lam[j] + dl[j];
+    // A refinement step that moved w by less than 2^-30 |w| has brought the
+    // error below 2^-30 of its previous size (error ~ (kappa u)^k): the next
+    // one could not change the FP64 weights.
+    if (it >= 1) {
+      const double upd = wave_max(live ? fabs(dd_to_double(r1) + g) : 0.0);
+      const double wmax = wave_max(live ? fabs(w.hi) : 0.0);
+      if (upd <= 0x1p-30 * wmax) break;
+    }
   }
   const double wq = live ? dd_to_double(w) : 0.0;
   // residual of all ic equations (including a dropped one), in dd
@@ -437,14 +457,10 @@ __global__ void k_prefix(PlanView v) {
 }
 
 // ---------------------------------------------------------------------------
-// Geometry at every quadrature point: F = sum_i C_i B_i and the Jacobian
-// J = dF/dzeta, whose column b is evaluated from the control net differenced
-// along b and the non-negative weights P N_{i,P-1} / (xi_{i+P} - xi_i) (no
-// cancellation, unlike sum_i C_i dB_i/dzeta_b); then det J and the
-// coefficient field (det J; K = a det J J^{-1} J^{-T}).
-template <int P, typename T, bool XPHYS>
-__global__ __launch_bounds__(256) void k_geometry(PlanView v, const double* __restrict__ coef,
-                                                  double* __restrict__ xphys) {
+// Physical coordinates F = sum_i C_i B_i at every quadrature point (used to
+// sample a coefficient given as a function of x).
+template <int P>
+__global__ __launch_bounds__(256) void k_xphys(PlanView v, double* __restrict__ xphys) {
   const int64_t q = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (q >= v.nqtot) return;
   const DirView d1 = v.dir[0], d2 = v.dir[1], d3 = v.dir[2];
@@ -452,120 +468,40 @@ __global__ __launch_bounds__(256) void k_geometry(PlanView v, const double* __re
   const int q2 = int((q / d1.nq) % d2.nq);
   const int q3 = int(q / (int64_t(d1.nq) * d2.nq));
   const int e1 = d1.qspan[q1], e2 = d2.qspan[q2], e3 = d3.qspan[q3];
-  // direction-1 tables in registers; weight of the difference C_{e+r} - C_{e+r-1}
-  // is w[r] (none for r = 0)
-  double v1[P + 1], w1[P + 1];
+  double v1[P + 1];
 #pragma unroll
-  for (int r = 0; r <= P; ++r) {
-    v1[r] = d1.bv[q1 * (P + 1) + r];
-    w1[r] = r ? d1.bw[q1 * P + r - 1] : 0.0;
-  }
+  for (int r = 0; r <= P; ++r) v1[r] = d1.bv[q1 * (P + 1) + r];
   const double* bv2 = d2.bv + q2 * (P + 1);
   const double* bv3 = d3.bv + q3 * (P + 1);
-  const double* bw2 = d2.bw + q2 * P - 1;   // bw2[r] for r >= 1
-  const double* bw3 = d3.bw + q3 * P - 1;
   const int n1 = d1.n, n2 = d2.n;
-  const size_t NC = size_t(n1) * n2 * d3.n * 3;
-  if (XPHYS) {
-    double F[3] = {0, 0, 0};
-#pragma unroll 1
-    for (int l3 = 0; l3 <= P; ++l3) {
-      double f2[3] = {0, 0, 0};
-#pragma unroll 1
-      for (int l2 = 0; l2 <= P; ++l2) {
-        const double* c = v.ctrl + ((size_t(e3 + l3) * n2 + (e2 + l2)) * n1 + e1) * 3;
-        double f1[3] = {0, 0, 0};
-#pragma unroll
-        for (int l1 = 0; l1 <= P; ++l1)
-#pragma unroll
-          for (int a = 0; a < 3; ++a) f1[a] += c[l1 * 3 + a] * v1[l1];
-        const double b2 = bv2[l2];
-#pragma unroll
-        for (int a = 0; a < 3; ++a) f2[a] += f1[a] * b2;
-      }
-      const double b3 = bv3[l3];
-#pragma unroll
-      for (int a = 0; a < 3; ++a) F[a] += f2[a] * b3;
-    }
-#pragma unroll
-    for (int a = 0; a < 3; ++a) xphys[q * 3 + a] = F[a];
-    return;
-  }
-  const double* C1 = v.dctrl;
-  const double* C2 = v.dctrl + NC;
-  const double* C3 = v.dctrl + 2 * NC;
-  double J[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+  double F[3] = {0, 0, 0};
 #pragma unroll 1
   for (int l3 = 0; l3 <= P; ++l3) {
-    double j02[3] = {0, 0, 0}, j12[3] = {0, 0, 0}, j22[3] = {0, 0, 0};
+    double f2[3] = {0, 0, 0};
 #pragma unroll 1
     for (int l2 = 0; l2 <= P; ++l2) {
-      const size_t o = ((size_t(e3 + l3) * n2 + (e2 + l2)) * n1 + e1) * 3;
-      double j01[3] = {0, 0, 0}, j11[3] = {0, 0, 0}, j21[3] = {0, 0, 0};
+      const double* c = v.ctrl + ((size_t(e3 + l3) * n2 + (e2 + l2)) * n1 + e1) * 3;
+      double f1[3] = {0, 0, 0};
 #pragma unroll
-      for (int l1 = 0; l1 <= P; ++l1) {
+      for (int l1 = 0; l1 <= P; ++l1)
 #pragma unroll
-        for (int a = 0; a < 3; ++a) {
-          const size_t k = o + l1 * 3 + a;
-          if (l1) j01[a] += C1[k] * w1[l1];
-          j11[a] += C2[k] * v1[l1];
-          j21[a] += C3[k] * v1[l1];
-        }
-      }
+        for (int a = 0; a < 3; ++a) f1[a] += c[l1 * 3 + a] * v1[l1];
       const double b2 = bv2[l2];
-      const double g2 = l2 ? bw2[l2] : 0.0;
 #pragma unroll
-      for (int a = 0; a < 3; ++a) {
-        j02[a] += j01[a] * b2;
-        j12[a] += j11[a] * g2;
-        j22[a] += j21[a] * b2;
-      }
+      for (int a = 0; a < 3; ++a) f2[a] += f1[a] * b2;
     }
     const double b3 = bv3[l3];
-    const double g3 = l3 ? bw3[l3] : 0.0;
 #pragma unroll
-    for (int a = 0; a < 3; ++a) {
-      J[a][0] += j02[a] * b3;
-      J[a][1] += j12[a] * b3;
-      J[a][2] += j22[a] * g3;
-    }
+    for (int a = 0; a < 3; ++a) F[a] += f2[a] * b3;
   }
-  // cofactors C_ab; adj(J) = C^T; det J = sum_b J_0b C_0b
-  const double c00 = J[1][1] * J[2][2] - J[1][2] * J[2][1];
-  const double c01 = J[1][2] * J[2][0] - J[1][0] * J[2][2];
-  const double c02 = J[1][0] * J[2][1] - J[1][1] * J[2][0];
-  const double c10 = J[0][2] * J[2][1] - J[0][1] * J[2][2];
-  const double c11 = J[0][0] * J[2][2] - J[0][2] * J[2][0];
-  const double c12 = J[0][1] * J[2][0] - J[0][0] * J[2][1];
-  const double c20 = J[0][1] * J[1][2] - J[0][2] * J[1][1];
-  const double c21 = J[0][2] * J[1][0] - J[0][0] * J[1][2];
-  const double c22 = J[0][0] * J[1][1] - J[0][1] * J[1][0];
-  const double det = J[0][0] * c00 + J[0][1] * c01 + J[0][2] * c02;
-  if (!(det > 0.0) || !isfinite(det)) {
-    atomicAdd(&v.flags[FLAG_DETJ_BAD], 1);
-    atomicMin(&v.flags[FLAG_DETJ_FIRST], int(q));
-  }
-  // K_lm = a * sum_k adj(J)_lk adj(J)_mk / det = a * sum_k C_kl C_km / det
-  const double s = (coef ? coef[q] : 1.0) / det;
-  const double K11 = s * (c00 * c00 + c10 * c10 + c20 * c20);
-  const double K22 = s * (c01 * c01 + c11 * c11 + c21 * c21);
-  const double K33 = s * (c02 * c02 + c12 * c12 + c22 * c22);
-  const double K12 = s * (c00 * c01 + c10 * c11 + c20 * c21);
-  const double K13 = s * (c00 * c02 + c10 * c12 + c20 * c22);
-  const double K23 = s * (c01 * c02 + c11 * c12 + c21 * c22);
-  T* f = static_cast<T*>(v.field);
-  const int64_t N = v.nqtot;
-  f[0 * N + q] = T(det);
-  f[1 * N + q] = T(K11);
-  f[2 * N + q] = T(K22);
-  f[3 * N + q] = T(K33);
-  f[4 * N + q] = T(K12);
-  f[5 * N + q] = T(K13);
-  f[6 * N + q] = T(K23);
+#pragma unroll
+  for (int a = 0; a < 3; ++a) xphys[q * 3 + a] = F[a];
 }
 
 // ---------------------------------------------------------------------------
-// CSR pattern: one wavefront per row.
+// CSR pattern: one wavefront per row.  A row's columns are (j3, j2, j1)
+// lexicographic; lanes run over the (j2, j1) plane, so each store of a lane
+// group is contiguous, and the j3 planes follow at a fixed stride.
 __global__ __launch_bounds__(256) void k_pattern(PlanView v, int64_t* __restrict__ row_ptr,
                                                  int32_t* __restrict__ col_idx) {
   const int lane = threadIdx.x & 63;
@@ -581,15 +517,143 @@ __global__ __launch_bounds__(256) void k_pattern(PlanView v, int64_t* __restrict
   i_range(i3, v.p, n3, is3, ic3);
   const int64_t T1 = d1.prefix[n1], T2 = d2.prefix[n2];
   const int64_t start = d3.prefix[i3] * T2 * T1 + int64_t(ic3) * (d2.prefix[i2] * T1 + int64_t(ic2) * d1.prefix[i1]);
-  const int len = ic1 * ic2 * ic3;
+  const int plane = ic1 * ic2;
   if (lane == 0) {
     row_ptr[row] = start;
-    if (row == nrows - 1) row_ptr[nrows] = start + len;
+    if (row == nrows - 1) row_ptr[nrows] = start + int64_t(plane) * ic3;
   }
-  for (int t = lane; t < len; t += 64) {
-    const int jj1 = t % ic1, tt = t / ic1, jj2 = tt % ic2, jj3 = tt / ic2;
-    col_idx[start + t] = (is1 + jj1) + n1 * ((is2 + jj2) + n2 * (is3 + jj3));
+  const int n12 = n1 * n2;
+  for (int t = lane; t < plane; t += 64) {
+    const int jj2 = t / ic1, jj1 = t - jj2 * ic1;
+    int col = (is1 + jj1) + n1 * (is2 + jj2) + n12 * is3;
+    int32_t* o = col_idx + start + t;
+    for (int jj3 = 0; jj3 < ic3; ++jj3) {
+      o[0] = col;
+      o += plane;
+      col += n12;
+    }
   }
+}
+
+// ---------------------------------------------------------------------------
+// Geometry by sum factorization, one direction at a time (three passes over
+// small intermediates instead of (p+1)^3 control points per quadrature
+// point).  With D_b the control net differenced along b and the weights
+// g_b(i) = p N_{i,p-1} / (xi_{i+p} - xi_i), the Jacobian columns are
+//   J_:,1 = sum_i D_1[i] g_1(i1) B_2(i2) B_3(i3)
+//   J_:,2 = sum_i D_2[i] B_1(i1) g_2(i2) B_3(i3)
+//   J_:,3 = sum_i D_3[i] B_1(i1) B_2(i2) g_3(i3).
+// Records hold the 3 nets x 3 coordinates (9 doubles).
+constexpr int kGeoRec = 9;
+
+// pass 3: X[q3][i2][i1][k, a] = sum_l3 D_k[e3 + l3][i2][i1][a] * (B_3 or g_3)
+template <int P>
+__global__ __launch_bounds__(256) void k_geo3(PlanView v, double* __restrict__ X) {
+  const DirView d1 = v.dir[0], d2 = v.dir[1], d3 = v.dir[2];
+  const int n1 = d1.n, n2 = d2.n;
+  const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (t >= int64_t(d3.nq) * n2 * n1) return;
+  const int i1 = int(t % n1), i2 = int((t / n1) % n2), q3 = int(t / (int64_t(n1) * n2));
+  const int e3 = d3.qspan[q3];
+  const size_t NC = size_t(n1) * n2 * d3.n * 3;
+  double acc[kGeoRec];
+#pragma unroll
+  for (int k = 0; k < kGeoRec; ++k) acc[k] = 0.0;
+#pragma unroll
+  for (int l = 0; l <= P; ++l) {
+    const double b = d3.bv[q3 * (P + 1) + l];
+    const double g = l ? d3.bw[q3 * P + l - 1] : 0.0;
+    const size_t o = ((size_t(e3 + l) * n2 + i2) * n1 + i1) * 3;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      acc[0 + a] += v.dctrl[o + a] * b;
+      acc[3 + a] += v.dctrl[NC + o + a] * b;
+      if (l) acc[6 + a] += v.dctrl[2 * NC + o + a] * g;
+    }
+  }
+  double* x = X + size_t(t) * kGeoRec;
+#pragma unroll
+  for (int k = 0; k < kGeoRec; ++k) x[k] = acc[k];
+}
+
+// pass 2: Y[q3][q2][i1][k, a] = sum_l2 X[q3][e2 + l2][i1][k, a] * (B_2 or g_2)
+template <int P>
+__global__ __launch_bounds__(256) void k_geo2(PlanView v, const double* __restrict__ X, double* __restrict__ Y) {
+  const DirView d1 = v.dir[0], d2 = v.dir[1], d3 = v.dir[2];
+  const int n1 = d1.n, n2 = d2.n, nq2 = d2.nq;
+  const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (t >= int64_t(d3.nq) * nq2 * n1) return;
+  const int i1 = int(t % n1), q2 = int((t / n1) % nq2), q3 = int(t / (int64_t(n1) * nq2));
+  const int e2 = d2.qspan[q2];
+  double acc[kGeoRec];
+#pragma unroll
+  for (int k = 0; k < kGeoRec; ++k) acc[k] = 0.0;
+#pragma unroll
+  for (int l = 0; l <= P; ++l) {
+    const double b = d2.bv[q2 * (P + 1) + l];
+    const double g = l ? d2.bw[q2 * P + l - 1] : 0.0;
+    const double* x = X + ((size_t(q3) * n2 + e2 + l) * n1 + i1) * kGeoRec;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      acc[0 + a] += x[0 + a] * b;
+      if (l) acc[3 + a] += x[3 + a] * g;
+      acc[6 + a] += x[6 + a] * b;
+    }
+  }
+  double* y = Y + size_t(t) * kGeoRec;
+#pragma unroll
+  for (int k = 0; k < kGeoRec; ++k) y[k] = acc[k];
+}
+
+// pass 1 and the point values: J from Y, then det J and the coefficients
+// (det J; K = a det J J^{-1} J^{-T} = a adj(J) adj(J)^T / det J)
+template <int P, typename T>
+__global__ __launch_bounds__(256) void k_geo1(PlanView v, const double* __restrict__ Y,
+                                              const double* __restrict__ coef) {
+  const int64_t q = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (q >= v.nqtot) return;
+  const DirView d1 = v.dir[0], d2 = v.dir[1];
+  const int n1 = d1.n, nq1 = d1.nq;
+  const int q1 = int(q % nq1);
+  const int64_t line = q / nq1;   // q3 * nq2 + q2
+  const int e1 = d1.qspan[q1];
+  double J[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+#pragma unroll
+  for (int l = 0; l <= P; ++l) {
+    const double b = d1.bv[q1 * (P + 1) + l];
+    const double g = l ? d1.bw[q1 * P + l - 1] : 0.0;
+    const double* y = Y + (size_t(line) * n1 + e1 + l) * kGeoRec;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      if (l) J[a][0] += y[0 + a] * g;
+      J[a][1] += y[3 + a] * b;
+      J[a][2] += y[6 + a] * b;
+    }
+  }
+  const double c00 = J[1][1] * J[2][2] - J[1][2] * J[2][1];
+  const double c01 = J[1][2] * J[2][0] - J[1][0] * J[2][2];
+  const double c02 = J[1][0] * J[2][1] - J[1][1] * J[2][0];
+  const double c10 = J[0][2] * J[2][1] - J[0][1] * J[2][2];
+  const double c11 = J[0][0] * J[2][2] - J[0][2] * J[2][0];
+  const double c12 = J[0][1] * J[2][0] - J[0][0] * J[2][1];
+  const double c20 = J[0][1] * J[1][2] - J[0][2] * J[1][1];
+  const double c21 = J[0][2] * J[1][0] - J[0][0] * J[1][2];
+  const double c22 = J[0][0] * J[1][1] - J[0][1] * J[1][0];
+  const double det = J[0][0] * c00 + J[0][1] * c01 + J[0][2] * c02;
+  if (!(det > 0.0) || !isfinite(det)) {
+    atomicAdd(&v.flags[FLAG_DETJ_BAD], 1);
+    atomicMin(&v.flags[FLAG_DETJ_FIRST], int(q));
+  }
+  const double s = (coef ? coef[q] : 1.0) / det;
+  T* f = static_cast<T*>(v.field);
+  const int64_t N = v.nqtot;
+  f[0 * N + q] = T(det);
+  f[1 * N + q] = T(s * (c00 * c00 + c10 * c10 + c20 * c20));
+  f[2 * N + q] = T(s * (c01 * c01 + c11 * c11 + c21 * c21));
+  f[3 * N + q] = T(s * (c02 * c02 + c12 * c12 + c22 * c22));
+  f[4 * N + q] = T(s * (c00 * c01 + c10 * c11 + c20 * c21));
+  f[5 * N + q] = T(s * (c00 * c02 + c10 * c12 + c20 * c22));
+  f[6 * N + q] = T(s * (c01 * c02 + c11 * c12 + c21 * c22));
 }
 
 template <int P>
@@ -606,21 +670,28 @@ hipError_t rules_p(const PlanView& v, hipStream_t s) {
   int maxn = 0;
   for (int k = 0; k < 3; ++k) maxn = v.dir[k].n > maxn ? v.dir[k].n : maxn;
   hipLaunchKernelGGL(k_rules<P>, dim3(maxn, 3), dim3(256), 0, s, v);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_prefix, dim3(1), dim3(64), 0, s, v);
   return hipGetLastError();
 }
 
 template <int P>
 hipError_t geometry_p(const PlanView& v, const double* coef, double* xphys, hipStream_t s) {
   const unsigned blocks = unsigned((v.nqtot + 255) / 256);
-  if (xphys)
-    hipLaunchKernelGGL((k_geometry<P, double, true>), dim3(blocks), dim3(256), 0, s, v, coef, xphys);
-  else if (v.prec == WQ_FP64)
-    hipLaunchKernelGGL((k_geometry<P, double, false>), dim3(blocks), dim3(256), 0, s, v, coef, xphys);
+  if (xphys) {
+    hipLaunchKernelGGL((k_xphys<P>), dim3(blocks), dim3(256), 0, s, v, xphys);
+    return hipGetLastError();
+  }
+  // the two intermediates live in the first-contraction buffer, which is
+  // rewritten by every assembly
+  const DirView &d1 = v.dir[0], &d2 = v.dir[1], &d3 = v.dir[2];
+  double* X = static_cast<double*>(v.ybuf);
+  const int64_t nx = int64_t(d3.nq) * d2.n * d1.n, ny = int64_t(d3.nq) * d2.nq * d1.n;
+  double* Y = X + nx * kGeoRec;
+  hipLaunchKernelGGL((k_geo3<P>), dim3(unsigned((nx + 255) / 256)), dim3(256), 0, s, v, X);
+  hipLaunchKernelGGL((k_geo2<P>), dim3(unsigned((ny + 255) / 256)), dim3(256), 0, s, v, X, Y);
+  if (v.prec == WQ_FP64)
+    hipLaunchKernelGGL((k_geo1<P, double>), dim3(blocks), dim3(256), 0, s, v, Y, coef);
   else
-    hipLaunchKernelGGL((k_geometry<P, float, false>), dim3(blocks), dim3(256), 0, s, v, coef, xphys);
+    hipLaunchKernelGGL((k_geo1<P, float>), dim3(blocks), dim3(256), 0, s, v, Y, coef);
   return hipGetLastError();
 }
 
@@ -652,6 +723,11 @@ hipError_t launch_geometry(const PlanView& v, const double* coef, double* xphys,
 #define C(P) geometry_p<P>(v, coef, xphys, s)
   WQ_DISPATCH_P(v.p, C)
 #undef C
+}
+
+hipError_t launch_prefix(const PlanView& v, hipStream_t s) {
+  hipLaunchKernelGGL(k_prefix, dim3(1), dim3(64), 0, s, v);
+  return hipGetLastError();
 }
 
 hipError_t launch_ctrl_diff(const PlanView& v, hipStream_t s) {
