@@ -56,22 +56,36 @@ namespace {
 enum : int { R00 = 0, R10 = 1, R01 = 2, R11 = 3 };
 
 // NW: wavefronts per workgroup; J3: trial indices j3 per workgroup (phase C
-// uses IC * J3 lanes); C: quadrature columns per chunk of phases A and B.
-template <int P, typename T> struct PushCfg;
-template <> struct PushCfg<2, double> { static constexpr int NW = 1, J3 = 5, C = 4; };
-template <> struct PushCfg<3, double> { static constexpr int NW = 1, J3 = 7, C = 4; };
-template <> struct PushCfg<4, double> { static constexpr int NW = 1, J3 = 5, C = 4; };
-template <> struct PushCfg<5, double> { static constexpr int NW = 2, J3 = 11, C = 2; };
-template <> struct PushCfg<6, double> { static constexpr int NW = 2, J3 = 7, C = 2; };
-template <> struct PushCfg<2, float> { static constexpr int NW = 1, J3 = 5, C = 8; };
-template <> struct PushCfg<3, float> { static constexpr int NW = 1, J3 = 7, C = 8; };
-template <> struct PushCfg<4, float> { static constexpr int NW = 1, J3 = 5, C = 8; };
-template <> struct PushCfg<5, float> { static constexpr int NW = 2, J3 = 11, C = 4; };
-template <> struct PushCfg<6, float> { static constexpr int NW = 2, J3 = 7, C = 4; };
+// uses IC * J3 lanes); C: quadrature columns per chunk of phases A and B
+// (phase B has J3 * C * 4 items for the stiffness).  Chosen by measurement.
+template <int P, typename T, bool STIFF> struct PushCfg;
+#define WQ_PUSH_CFG(P_, T_, S_, NW_, J3_, C_) \
+  template <> struct PushCfg<P_, T_, S_> { static constexpr int NW = NW_, J3 = J3_, C = C_; };
+WQ_PUSH_CFG(2, double, false, 1, 5, 4)
+WQ_PUSH_CFG(2, double, true, 1, 5, 3)
+WQ_PUSH_CFG(3, double, false, 1, 7, 4)
+WQ_PUSH_CFG(3, double, true, 1, 7, 2)
+WQ_PUSH_CFG(4, double, false, 1, 5, 4)
+WQ_PUSH_CFG(4, double, true, 1, 5, 3)
+WQ_PUSH_CFG(5, double, false, 2, 11, 4)
+WQ_PUSH_CFG(5, double, true, 2, 11, 2)
+WQ_PUSH_CFG(6, double, false, 2, 7, 4)
+WQ_PUSH_CFG(6, double, true, 2, 7, 1)
+WQ_PUSH_CFG(2, float, false, 1, 5, 8)
+WQ_PUSH_CFG(2, float, true, 1, 5, 3)
+WQ_PUSH_CFG(3, float, false, 1, 7, 8)
+WQ_PUSH_CFG(3, float, true, 1, 7, 2)
+WQ_PUSH_CFG(4, float, false, 1, 5, 8)
+WQ_PUSH_CFG(4, float, true, 1, 5, 3)
+WQ_PUSH_CFG(5, float, false, 2, 11, 4)
+WQ_PUSH_CFG(5, float, true, 2, 11, 2)
+WQ_PUSH_CFG(6, float, false, 2, 7, 8)
+WQ_PUSH_CFG(6, float, true, 2, 7, 2)
+#undef WQ_PUSH_CFG
 
 template <int P, typename T, bool STIFF>
 struct Shape {
-  using Cfg = PushCfg<P, T>;
+  using Cfg = PushCfg<P, T, STIFF>;
   static constexpr int IC = 2 * P + 1, QC = 3 * P + 1;
   static constexpr int NT = 64 * Cfg::NW, J3 = Cfg::J3, C = Cfg::C;
   static constexpr int NPART = (IC + J3 - 1) / J3;        // j3 parts
