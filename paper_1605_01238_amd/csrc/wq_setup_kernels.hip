@@ -177,10 +177,29 @@ __global__ __launch_bounds__(256) void k_rules(PlanView v) {
   __shared__ dd bvec[4][IC];
   __shared__ double Rl[4][IC][IC];
 
+  // A^(alpha)[jj][qq] = B^(alpha)_{is+jj}(x_{qs+qq}) in double-double
+  // (wave 0), while wave 1 forms the Gauss-Legendre rule.
+  for (int idx = tid; idx < 2 * IC * QC; idx += 256) (&A[0][0][0])[idx] = dd{0.0, 0.0};
+  __syncthreads();
+  for (int qq = tid; qq < qc; qq += 256) {
+    int e;
+    const dd x = qp_coord(d.knots, P, nel, qs + qq, e);
+    dd N[P + 1], D[P + 1];
+    basis_funs<P, dd>(d.knots, e + P, x, N, D);
+#pragma unroll
+    for (int r = 0; r <= P; ++r) {
+      const int jj = e + r - is;
+      if (jj >= 0 && jj < ic) {
+        A[0][jj][qq] = N[r];
+        A[1][jj][qq] = D[r];
+      }
+    }
+  }
   // Gauss-Legendre nodes/weights on [-1, 1]: Newton's method on the
   // Legendre polynomial P_NG, in FP64 to convergence, then in double-double.
-  if (tid < NG) {
-    double z = cos(M_PI * (tid + 0.75) / (NG + 0.5));
+  if (tid >= 64 && tid < 64 + NG) {
+    const int t = tid - 64;
+    double z = cos(M_PI * (t + 0.75) / (NG + 0.5));
     for (int it = 0; it < 100; ++it) {
       double p0 = 1.0, p1 = z;
       for (int k = 2; k <= NG; ++k) {
@@ -203,25 +222,8 @@ __global__ __launch_bounds__(256) void k_rules(PlanView v) {
       dp = ((zz * p1 - p0) * double(NG)) / (zz * zz - 1.0);
       if (it < 2) zz = zz - p1 / dp;
     }
-    gx[tid] = zz;
-    gw[tid] = 2.0 / ((1.0 - zz * zz) * (dp * dp));
-  }
-  // A^(alpha)[jj][qq] = B^(alpha)_{is+jj}(x_{qs+qq}) in double-double.
-  for (int idx = tid; idx < 2 * IC * QC; idx += 256) (&A[0][0][0])[idx] = dd{0.0, 0.0};
-  __syncthreads();
-  for (int qq = tid; qq < qc; qq += 256) {
-    int e;
-    const dd x = qp_coord(d.knots, P, nel, qs + qq, e);
-    dd N[P + 1], D[P + 1];
-    basis_funs<P, dd>(d.knots, e + P, x, N, D);
-#pragma unroll
-    for (int r = 0; r <= P; ++r) {
-      const int jj = e + r - is;
-      if (jj >= 0 && jj < ic) {
-        A[0][jj][qq] = N[r];
-        A[1][jj][qq] = D[r];
-      }
-    }
+    gx[t] = zz;
+    gw[t] = 2.0 / ((1.0 - zz * zz) * (dp * dp));
   }
   __syncthreads();
   // B-splines at the Gauss points of the knot-spans supporting B_i.
@@ -244,18 +246,31 @@ __global__ __launch_bounds__(256) void k_rules(PlanView v) {
     gspan[g] = e;
   }
   __syncthreads();
-  // Exact 1D integrals (degree <= 2p per span, p+1 Gauss points), in dd.
-  for (int idx = tid; idx < 4 * IC; idx += 256) {
-    const int pair = idx / IC, jj = idx % IC, al = pair & 1, be = pair >> 1;
+  // Exact 1D integrals (degree <= 2p per span, p+1 Gauss points), in dd:
+  // one partial sum per (pairing, jj, span), then the sum over the spans.
+  __shared__ dd part[4][IC][P + 1];
+  for (int idx = tid; idx < 4 * IC * (P + 1); idx += 256) {
+    const int sp = idx % (P + 1), jj = (idx / (P + 1)) % IC, pair = idx / ((P + 1) * IC);
+    const int al = pair & 1, be = pair >> 1;
     dd s{0.0, 0.0};
-    if (jj < ic) {
-      const int j = is + jj;
-      for (int g = 0; g < ng; ++g) {
-        const int ri = i - gspan[g], rj = j - gspan[g];
-        if (ri >= 0 && ri <= P && rj >= 0 && rj <= P)
+    if (jj < ic && sp < e1 - e0) {
+      const int j = is + jj, e = e0 + sp, ri = i - e, rj = j - e;
+      if (ri >= 0 && ri <= P && rj >= 0 && rj <= P) {
+#pragma unroll
+        for (int t = 0; t < NG; ++t) {
+          const int g = sp * NG + t;
           s += gwt[g] * (be ? gder[g][ri] : gval[g][ri]) * (al ? gder[g][rj] : gval[g][rj]);
+        }
       }
     }
+    part[pair][jj][sp] = s;
+  }
+  __syncthreads();
+  for (int idx = tid; idx < 4 * IC; idx += 256) {
+    const int pair = idx / IC, jj = idx % IC;
+    dd s{0.0, 0.0};
+#pragma unroll
+    for (int sp = 0; sp <= P; ++sp) s += part[pair][jj][sp];
     bvec[pair][jj] = s;
   }
   __syncthreads();
@@ -285,13 +300,12 @@ __global__ __launch_bounds__(256) void k_rules(PlanView v) {
         const double vnorm2 = 2.0 * (nrm2 + fabs(akk) * nrm);
         vk[k] = vv;
         vn[k] = vnorm2;
+        // columns j >= r are zero and stay zero
+        double sj[IC];
 #pragma unroll
-        for (int j = 0; j < IC; ++j) {
-          if (j >= k && j < r) {
-            const double s = wave_sum(vv * m[j]);
-            m[j] -= (2.0 * s / vnorm2) * vv;
-          }
-        }
+        for (int j = k; j < IC; ++j) sj[j] = wave_sum(vv * m[j]);
+#pragma unroll
+        for (int j = k; j < IC; ++j) m[j] -= (2.0 * sj[j] / vnorm2) * vv;
       } else {
         broke = true;
       }
@@ -315,15 +329,14 @@ __global__ __launch_bounds__(256) void k_rules(PlanView v) {
     // r2 = b - A w (kept equations), r1 = A^T lam - w (this lane)
     double r2[IC];
     dd r1 = -w;
+    // all IC rows (zero beyond #I_i; a dropped row is computed and unused,
+    // its multiplier stays 0), so the IC reductions are independent
 #pragma unroll
     for (int j = 0; j < IC; ++j) {
-      r2[j] = 0.0;
-      if (j < r) {
-        const dd a = live ? A[al][j][lane] : dd{0.0, 0.0};
-        const dd s = dd_wave_sum(a * w);
-        r2[j] = dd_to_double(bvec[pair][j] - s);
-        r1 += a * lam[j];
-      }
+      const dd a = live ? A[al][j][lane] : dd{0.0, 0.0};
+      const dd s = dd_wave_sum(a * w);
+      r2[j] = dd_to_double(bvec[pair][j] - s);
+      r1 += a * lam[j];
     }
     // t = (Q^T r1)[0:r]: apply H_0 .. H_{r-1}
     double u = live ? dd_to_double(r1) : 0.0;
@@ -381,7 +394,8 @@ __global__ __launch_bounds__(256) void k_rules(PlanView v) {
   const double wq = live ? dd_to_double(w) : 0.0;
   // residual of all ic equations (including a dropped one), in dd
   double bmax = 0.0, rmax = 0.0;
-  for (int j = 0; j < ic; ++j) {
+#pragma unroll
+  for (int j = 0; j < IC; ++j) {   // rows beyond #I_i are zero on both sides
     const dd a = live ? A[al][j][lane] : dd{0.0, 0.0};
     const dd s = dd_wave_sum(a * wq);
     bmax = fmax(bmax, fabs(bvec[pair][j].hi));
