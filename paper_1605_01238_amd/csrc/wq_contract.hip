@@ -69,8 +69,8 @@ WQ_PUSH_CFG(4, double, false, 1, 5, 4)
 WQ_PUSH_CFG(4, double, true, 1, 5, 3)
 WQ_PUSH_CFG(5, double, false, 2, 11, 4)
 WQ_PUSH_CFG(5, double, true, 2, 11, 2)
-WQ_PUSH_CFG(6, double, false, 2, 7, 4)
-WQ_PUSH_CFG(6, double, true, 2, 7, 1)
+WQ_PUSH_CFG(6, double, false, 1, 4, 8)
+WQ_PUSH_CFG(6, double, true, 4, 13, 2)
 WQ_PUSH_CFG(2, float, false, 1, 5, 8)
 WQ_PUSH_CFG(2, float, true, 1, 5, 3)
 WQ_PUSH_CFG(3, float, false, 1, 7, 8)
@@ -79,8 +79,8 @@ WQ_PUSH_CFG(4, float, false, 1, 5, 8)
 WQ_PUSH_CFG(4, float, true, 1, 5, 3)
 WQ_PUSH_CFG(5, float, false, 2, 11, 4)
 WQ_PUSH_CFG(5, float, true, 2, 11, 2)
-WQ_PUSH_CFG(6, float, false, 2, 7, 8)
-WQ_PUSH_CFG(6, float, true, 2, 7, 2)
+WQ_PUSH_CFG(6, float, false, 3, 13, 8)
+WQ_PUSH_CFG(6, float, true, 3, 13, 2)
 #undef WQ_PUSH_CFG
 
 template <int P, typename T, bool STIFF>
