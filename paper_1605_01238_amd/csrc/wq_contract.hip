@@ -46,7 +46,7 @@
 // Pencils are split into runs of rows until the grid holds about this many
 // workgroups.
 #ifndef WQ_WG_TARGET
-#define WQ_WG_TARGET 4096
+#define WQ_WG_TARGET 2048
 #endif
 
 namespace wq {
@@ -66,7 +66,7 @@ WQ_PUSH_CFG(2, double, true, 1, 5, 3)
 WQ_PUSH_CFG(3, double, false, 1, 7, 4)
 WQ_PUSH_CFG(3, double, true, 1, 7, 2)
 WQ_PUSH_CFG(4, double, false, 1, 5, 4)
-WQ_PUSH_CFG(4, double, true, 1, 5, 3)
+WQ_PUSH_CFG(4, double, true, 2, 9, 2)
 WQ_PUSH_CFG(5, double, false, 2, 11, 4)
 WQ_PUSH_CFG(5, double, true, 2, 11, 2)
 WQ_PUSH_CFG(6, double, false, 1, 4, 8)
