@@ -156,7 +156,13 @@ MID_P4 = Workload("p4_32el_perturbed_coef", 4, (32, 32, 32), geom_seed=2, coef_s
 LARGE_P6 = Workload("p6_64el_twisted", 6, (64, 64, 64), geom_seed=4, coef_seed=None,
                     twist_deg=30.0, which=("stiff", "mass"))
 
-WORKLOADS = {w.name: w for w in (SMALL_P2, MID_P4, LARGE_P6)}
+# the p = 4..6 x {32^3, 64^3} sweep (same recipe as MID_P4: perturbed
+# Greville net, smooth coefficient, stiffness)
+SWEEP = tuple(Workload(f"p{p}_{e}el_perturbed_coef", p, (e, e, e), geom_seed=10 + p, coef_seed=20 + p,
+                       which=("stiff",))
+              for p, e in ((4, 64), (5, 32), (5, 64), (6, 32)))
+
+WORKLOADS = {w.name: w for w in (SMALL_P2, MID_P4, LARGE_P6) + SWEEP}
 
 
 def sample_rows(n_dof3, p: int, n_uniform: int, n_boundary: int, seed: int) -> np.ndarray:
