@@ -128,8 +128,7 @@ namespace wq {
 hipError_t launch_points(const PlanView& v, hipStream_t s);
 hipError_t launch_rules(const PlanView& v, hipStream_t s);
 hipError_t launch_prefix(const PlanView& v, hipStream_t s);
-hipError_t launch_ctrl_diff(const PlanView& v, hipStream_t s);
-hipError_t launch_coltab(const PlanView& v, hipStream_t s);
+hipError_t launch_ctrl_diff(const PlanView& v, const double* ctrl, hipStream_t s);
 hipError_t launch_geometry(const PlanView& v, const double* coef, double* xphys_out, hipStream_t s);
 hipError_t launch_pattern(const PlanView& v, int64_t* row_ptr, int32_t* col_idx, hipStream_t s);
 hipError_t launch_assemble(const PlanView& v, int which, void* mass, void* stiff, hipStream_t s);

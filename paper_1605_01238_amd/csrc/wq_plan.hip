@@ -244,20 +244,17 @@ wq_status wq_setup(wq_plan* plan, const double* ctrl_dev, const double* coef_dev
   if (!plan) return WQ_EINVAL;
   if (!plan->bound) return fail(plan, WQ_ESTATE, "wq_setup before wq_bind");
   if (!ctrl_dev) return fail(plan, WQ_EINVAL, "null control net");
-  hipError_t e = hipMemcpyAsync(plan->ws + plan->lay.ctrl, ctrl_dev, size_t(plan->nrows) * 3 * 8,
-                                hipMemcpyDeviceToDevice, stream);
-  if (e != hipSuccess) return hip_fail(plan, e, "wq_setup: control net copy");
   wq::PlanView v = plan->view();
+  hipError_t e;
   // univariate stage on the second stream, after everything already queued
   // on `stream` (earlier assemblies read the tables it rewrites)
   e = hipEventRecord(plan->ev_fork, stream);
   if (e == hipSuccess) e = hipStreamWaitEvent(plan->aux, plan->ev_fork, 0);
   if (e == hipSuccess) e = wq::launch_rules(v, plan->aux);
-  if (e == hipSuccess) e = wq::launch_coltab(v, plan->aux);
   if (e == hipSuccess) e = hipEventRecord(plan->ev_rules, plan->aux);
   if (e != hipSuccess) return hip_fail(plan, e, "wq_setup: univariate kernel");
   plan->rules_launched = true;
-  e = wq::launch_ctrl_diff(v, stream);
+  e = wq::launch_ctrl_diff(v, ctrl_dev, stream);
   if (e != hipSuccess) return hip_fail(plan, e, "wq_setup: control-net differences");
   e = wq::launch_geometry(v, coef_dev, nullptr, stream);
   if (e != hipSuccess) return hip_fail(plan, e, "wq_setup: geometry kernel");

@@ -111,6 +111,21 @@ __global__ __launch_bounds__(256) void k_points(PlanView v) {
     d.bv[q * (P + 1) + r] = N[r];
     d.bd[q * (P + 1) + r] = D[r];
   }
+  // column table of q: the basis part here, the weights by the rule solves
+  // (entries of rows without x_q strictly inside their support stay 0)
+  constexpr int NCT = 6 * (P + 1);
+#pragma unroll
+  for (int k = 0; k < 4 * (P + 1); ++k) {
+    d.colt64[q * NCT + k] = 0.0;
+    d.colt32[q * NCT + k] = 0.0f;
+  }
+#pragma unroll
+  for (int r = 0; r <= P; ++r) {
+    d.colt64[q * NCT + 4 * (P + 1) + r] = N[r];
+    d.colt64[q * NCT + 5 * (P + 1) + r] = D[r];
+    d.colt32[q * NCT + 4 * (P + 1) + r] = float(N[r]);
+    d.colt32[q * NCT + 5 * (P + 1) + r] = float(D[r]);
+  }
   // derivative of a spline: sum_i C_i B_i' = sum_i (C_i - C_{i-1}) P N_{i,P-1} / (xi_{i+P} - xi_i)
 #pragma unroll
   for (int r = 0; r < P; ++r) {
@@ -121,7 +136,7 @@ __global__ __launch_bounds__(256) void k_points(PlanView v) {
 
 // Differenced control net along each direction b: C_i - C_{i - e_b} (exact
 // inputs, so each difference is correctly rounded); zero where i_b = 0.
-__global__ __launch_bounds__(256) void k_ctrl_diff(PlanView v) {
+__global__ __launch_bounds__(256) void k_ctrl_diff(PlanView v, const double* __restrict__ src) {
   const int n1 = v.dir[0].n, n2 = v.dir[1].n, n3 = v.dir[2].n;
   const int64_t N = int64_t(n1) * n2 * n3;
   const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
@@ -129,10 +144,11 @@ __global__ __launch_bounds__(256) void k_ctrl_diff(PlanView v) {
   const int64_t i = t / 3;
   const int a = int(t % 3);
   const int i1 = int(i % n1), i2 = int((i / n1) % n2), i3 = int(i / (int64_t(n1) * n2));
-  const double c = v.ctrl[t];
-  v.dctrl[0 * N * 3 + t] = i1 > 0 ? c - v.ctrl[(i - 1) * 3 + a] : 0.0;
-  v.dctrl[1 * N * 3 + t] = i2 > 0 ? c - v.ctrl[(i - n1) * 3 + a] : 0.0;
-  v.dctrl[2 * N * 3 + t] = i3 > 0 ? c - v.ctrl[(i - int64_t(n1) * n2) * 3 + a] : 0.0;
+  const double c = src[t];
+  v.ctrl[t] = c;   // the plan keeps its own copy of the net
+  v.dctrl[0 * N * 3 + t] = i1 > 0 ? c - src[(i - 1) * 3 + a] : 0.0;
+  v.dctrl[1 * N * 3 + t] = i2 > 0 ? c - src[(i - n1) * 3 + a] : 0.0;
+  v.dctrl[2 * N * 3 + t] = i3 > 0 ? c - src[(i - int64_t(n1) * n2) * 3 + a] : 0.0;
 }
 
 // ---------------------------------------------------------------------------
@@ -408,6 +424,11 @@ __global__ __launch_bounds__(256) void k_rules(PlanView v) {
     }
   }
   // outputs (lane = local quadrature point qq; zero beyond #Q_i and #I_i)
+  if (lane < qc) {   // row i is slot i - e of the column table of its point
+    const int q = qs + lane, sl = i - d.qspan[q];
+    d.colt64[q * (6 * (P + 1)) + sl * 4 + pair] = wq;
+    d.colt32[q * (6 * (P + 1)) + sl * 4 + pair] = float(wq);
+  }
   if (lane < QC) {
     d.w[(size_t(pair) * n + i) * QC + lane] = wq;
     const size_t pq = size_t(i) * QC + lane;
@@ -425,34 +446,6 @@ __global__ __launch_bounds__(256) void k_rules(PlanView v) {
       }
     }
   }
-}
-
-// Per-point tables of direction `blockIdx.y` (see DirView::colt64): one
-// thread per (q, entry).
-template <int P>
-__global__ __launch_bounds__(256) void k_coltab(PlanView v) {
-  constexpr int QC = 3 * P + 1, NCT = 6 * (P + 1);
-  const DirView d = v.dir[blockIdx.y];
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= d.nq * NCT) return;
-  const int q = t / NCT, k = t % NCT;
-  const int e = d.qspan[q];
-  double val;
-  if (k < 4 * (P + 1)) {
-    const int s = k / 4, o = k % 4, i = e + s;
-    val = 0.0;
-    if (i < d.n) {
-      int qs, qc;
-      q_range(i, P, d.nel, qs, qc);
-      if (q >= qs && q < qs + qc) val = d.w[(size_t(o) * d.n + i) * QC + (q - qs)];
-    }
-  } else if (k < 5 * (P + 1)) {
-    val = d.bv[q * (P + 1) + (k - 4 * (P + 1))];
-  } else {
-    val = d.bd[q * (P + 1) + (k - 5 * (P + 1))];
-  }
-  d.colt64[t] = val;
-  d.colt32[t] = float(val);
 }
 
 // Prefix sums of the 1D row lengths #I_i (one thread per direction).
@@ -744,25 +737,10 @@ hipError_t launch_prefix(const PlanView& v, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_ctrl_diff(const PlanView& v, hipStream_t s) {
+hipError_t launch_ctrl_diff(const PlanView& v, const double* ctrl, hipStream_t s) {
   const int64_t N = int64_t(v.dir[0].n) * v.dir[1].n * v.dir[2].n * 3;
-  hipLaunchKernelGGL(k_ctrl_diff, dim3(unsigned((N + 255) / 256)), dim3(256), 0, s, v);
+  hipLaunchKernelGGL(k_ctrl_diff, dim3(unsigned((N + 255) / 256)), dim3(256), 0, s, v, ctrl);
   return hipGetLastError();
-}
-
-template <int P>
-hipError_t coltab_p(const PlanView& v, hipStream_t s) {
-  int maxq = 0;
-  for (int k = 0; k < 3; ++k) maxq = v.dir[k].nq > maxq ? v.dir[k].nq : maxq;
-  const int work = maxq * 6 * (P + 1);
-  hipLaunchKernelGGL(k_coltab<P>, dim3((work + 255) / 256, 3), dim3(256), 0, s, v);
-  return hipGetLastError();
-}
-
-hipError_t launch_coltab(const PlanView& v, hipStream_t s) {
-#define C(P) coltab_p<P>(v, s)
-  WQ_DISPATCH_P(v.p, C)
-#undef C
 }
 
 hipError_t launch_pattern(const PlanView& v, int64_t* row_ptr, int32_t* col_idx, hipStream_t s) {
