@@ -18,6 +18,39 @@ struct dd {
   double hi, lo;
 };
 
+// ---------------------------------------------------------------------------
+// Wavefront (64-lane) reductions through DPP lane moves (register to
+// register, no LDS round trip).  Steps: pairs and quads within a row of 16
+// (quad_perm), half-rows (row_half_mirror), rows (row_mirror), then rows 0+1
+// into row 1 and 2+3 into row 3 (row_bcast:15), and rows 0..1 into rows 2..3
+// (row_bcast:31); lane 63 ends with the total, read back as a uniform value.
+// Lanes of rows that a step leaves out receive 0.
+template <int CTRL, int ROW_MASK>
+__device__ inline double dpp_f64(double x) {
+  const long long b = __double_as_longlong(x);
+  const int lo = __builtin_amdgcn_update_dpp(0, int(b), CTRL, ROW_MASK, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, int(b >> 32), CTRL, ROW_MASK, 0xF, false);
+  return __longlong_as_double((long long)(unsigned)lo | ((long long)hi << 32));
+}
+
+__device__ inline double lane_f64(double x, int lane) {
+  const long long b = __double_as_longlong(x);
+  const int lo = __builtin_amdgcn_readlane(int(b), lane);
+  const int hi = __builtin_amdgcn_readlane(int(b >> 32), lane);
+  return __longlong_as_double((long long)(unsigned)lo | ((long long)hi << 32));
+}
+
+template <typename Op>
+__device__ inline double wave_reduce(double x, Op op) {
+  x = op(x, dpp_f64<0xB1, 0xF>(x));    // quad_perm [1,0,3,2]
+  x = op(x, dpp_f64<0x4E, 0xF>(x));    // quad_perm [2,3,0,1]
+  x = op(x, dpp_f64<0x141, 0xF>(x));   // row_half_mirror
+  x = op(x, dpp_f64<0x140, 0xF>(x));   // row_mirror
+  x = op(x, dpp_f64<0x142, 0xA>(x));   // row_bcast:15 -> rows 1, 3
+  x = op(x, dpp_f64<0x143, 0xC>(x));   // row_bcast:31 -> rows 2, 3
+  return lane_f64(x, 63);
+}
+
 __device__ inline dd dd_from(double a) { return dd{a, 0.0}; }
 
 __device__ inline dd two_sum(double a, double b) {
@@ -106,14 +139,16 @@ __device__ inline dd dd_sqrt(dd a) {
 __device__ inline double dd_to_double(dd a) { return a.hi + a.lo; }
 
 // Wavefront-wide sums (64 lanes) by butterfly exchange.
+// Sum over the wavefront in double-double (same DPP steps as wave_reduce).
 __device__ inline dd dd_wave_sum(dd x) {
 #pragma clang fp contract(off)
-#pragma unroll
-  for (int off = 32; off >= 1; off >>= 1) {
-    dd y{__shfl_xor(x.hi, off, 64), __shfl_xor(x.lo, off, 64)};
-    x = x + y;
-  }
-  return x;
+  x = x + dd{dpp_f64<0xB1, 0xF>(x.hi), dpp_f64<0xB1, 0xF>(x.lo)};
+  x = x + dd{dpp_f64<0x4E, 0xF>(x.hi), dpp_f64<0x4E, 0xF>(x.lo)};
+  x = x + dd{dpp_f64<0x141, 0xF>(x.hi), dpp_f64<0x141, 0xF>(x.lo)};
+  x = x + dd{dpp_f64<0x140, 0xF>(x.hi), dpp_f64<0x140, 0xF>(x.lo)};
+  x = x + dd{dpp_f64<0x142, 0xA>(x.hi), dpp_f64<0x142, 0xA>(x.lo)};
+  x = x + dd{dpp_f64<0x143, 0xC>(x.hi), dpp_f64<0x143, 0xC>(x.lo)};
+  return dd{lane_f64(x.hi, 63), lane_f64(x.lo, 63)};
 }
 
 }  // namespace wq

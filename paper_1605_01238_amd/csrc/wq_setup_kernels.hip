@@ -78,15 +78,11 @@ __device__ inline dd qp_coord(const double* __restrict__ k, int P, int nel, int 
 }
 
 __device__ inline double wave_max(double x) {
-#pragma unroll
-  for (int off = 32; off >= 1; off >>= 1) x = fmax(x, __shfl_xor(x, off, 64));
-  return x;
+  return wave_reduce(x, [](double a, double b) { return fmax(a, b); });
 }
 
 __device__ inline double wave_sum(double x) {
-#pragma unroll
-  for (int off = 32; off >= 1; off >>= 1) x += __shfl_xor(x, off, 64);
-  return x;
+  return wave_reduce(x, [](double a, double b) { return a + b; });
 }
 
 // ---------------------------------------------------------------------------
@@ -308,7 +304,7 @@ __global__ __launch_bounds__(256) void k_rules(PlanView v) {
     if (k < r) {
       const double xk = (lane >= k) ? m[k] : 0.0;
       const double nrm2 = wave_sum(xk * xk);
-      const double akk = __shfl(m[k], k, 64);
+      const double akk = lane_f64(m[k], k);
       if (nrm2 > 0.0) {
         const double nrm = sqrt(nrm2);
         const double alpha = akk >= 0.0 ? -nrm : nrm;
@@ -370,7 +366,7 @@ __global__ __launch_bounds__(256) void k_rules(PlanView v) {
 #pragma unroll
         for (int mm = 0; mm < k; ++mm) acc -= Rl[pair][mm][k] * z[mm];
         z[k] = acc / Rl[pair][k][k];
-        sv[k] = z[k] - __shfl(u, k, 64);
+        sv[k] = z[k] - lane_f64(u, k);
       }
     }
     // dlam = R^{-1} s (back substitution)
