@@ -503,8 +503,9 @@ __global__ __launch_bounds__(256) void k_xphys(PlanView v, double* __restrict__ 
 
 // ---------------------------------------------------------------------------
 // CSR pattern: one wavefront per row.  A row's columns are (j3, j2, j1)
-// lexicographic; lanes run over the (j2, j1) plane, so each store of a lane
-// group is contiguous, and the j3 planes follow at a fixed stride.
+// lexicographic.  Lanes write 16-byte groups of 4 consecutive entries (the
+// first group starts at the first 16-byte boundary of the row; the few
+// entries before it and after the last full group are written singly).
 __global__ __launch_bounds__(256) void k_pattern(PlanView v, int64_t* __restrict__ row_ptr,
                                                  int32_t* __restrict__ col_idx) {
   const int lane = threadIdx.x & 63;
@@ -520,21 +521,40 @@ __global__ __launch_bounds__(256) void k_pattern(PlanView v, int64_t* __restrict
   i_range(i3, v.p, n3, is3, ic3);
   const int64_t T1 = d1.prefix[n1], T2 = d2.prefix[n2];
   const int64_t start = d3.prefix[i3] * T2 * T1 + int64_t(ic3) * (d2.prefix[i2] * T1 + int64_t(ic2) * d1.prefix[i1]);
-  const int plane = ic1 * ic2;
+  const int plane = ic1 * ic2, len = plane * ic3;
   if (lane == 0) {
     row_ptr[row] = start;
-    if (row == nrows - 1) row_ptr[nrows] = start + int64_t(plane) * ic3;
+    if (row == nrows - 1) row_ptr[nrows] = start + len;
   }
   const int n12 = n1 * n2;
-  for (int t = lane; t < plane; t += 64) {
-    const int jj2 = t / ic1, jj1 = t - jj2 * ic1;
-    int col = (is1 + jj1) + n1 * (is2 + jj2) + n12 * is3;
-    int32_t* o = col_idx + start + t;
-    for (int jj3 = 0; jj3 < ic3; ++jj3) {
-      o[0] = col;
-      o += plane;
-      col += n12;
+  const int base = is1 + n1 * is2 + n12 * is3;
+  // column of entry t of the row
+  auto col_of = [&](int t) {
+    const int jj3 = t / plane, r = t - jj3 * plane, jj2 = r / ic1, jj1 = r - jj2 * ic1;
+    return base + jj1 + n1 * jj2 + n12 * jj3;
+  };
+  const int head = min(len, int((4 - (start & 3)) & 3));   // entries before the first boundary
+  const int ngroups = (len - head) >> 2;
+  if (lane < head) col_idx[start + lane] = col_of(lane);
+  const int tail0 = head + 4 * ngroups;
+  if (lane < len - tail0) col_idx[start + tail0 + lane] = col_of(tail0 + lane);
+  int4* __restrict__ o = reinterpret_cast<int4*>(col_idx + start + head);
+  for (int g = lane; g < ngroups; g += 64) {
+    const int t = head + 4 * g;
+    int jj3 = t / plane, r = t - jj3 * plane, jj2 = r / ic1, jj1 = r - jj2 * ic1;
+    int c[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      c[k] = base + jj1 + n1 * jj2 + n12 * jj3;
+      if (++jj1 == ic1) {
+        jj1 = 0;
+        if (++jj2 == ic2) {
+          jj2 = 0;
+          ++jj3;
+        }
+      }
     }
+    o[g] = int4{c[0], c[1], c[2], c[3]};
   }
 }
 
