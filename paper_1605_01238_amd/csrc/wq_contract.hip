@@ -57,30 +57,31 @@ enum : int { R00 = 0, R10 = 1, R01 = 2, R11 = 3 };
 
 // NW: wavefronts per workgroup; J3: trial indices j3 per workgroup (phase C
 // uses IC * J3 lanes); C: quadrature columns per chunk of phases A and B
-// (phase B has J3 * C * 4 items for the stiffness).  Chosen by measurement.
+// (phase B has J3 * C * 4 items for the stiffness); WPE: waves per SIMD the
+// register allocation must allow (0: no bound).  Chosen by measurement.
 template <int P, typename T, bool STIFF> struct PushCfg;
-#define WQ_PUSH_CFG(P_, T_, S_, NW_, J3_, C_) \
-  template <> struct PushCfg<P_, T_, S_> { static constexpr int NW = NW_, J3 = J3_, C = C_; };
-WQ_PUSH_CFG(2, double, false, 1, 5, 4)
-WQ_PUSH_CFG(2, double, true, 1, 5, 3)
-WQ_PUSH_CFG(3, double, false, 1, 7, 4)
-WQ_PUSH_CFG(3, double, true, 1, 7, 2)
-WQ_PUSH_CFG(4, double, false, 1, 5, 4)
-WQ_PUSH_CFG(4, double, true, 2, 9, 2)
-WQ_PUSH_CFG(5, double, false, 2, 11, 4)
-WQ_PUSH_CFG(5, double, true, 2, 11, 2)
-WQ_PUSH_CFG(6, double, false, 1, 4, 8)
-WQ_PUSH_CFG(6, double, true, 4, 13, 2)
-WQ_PUSH_CFG(2, float, false, 1, 5, 8)
-WQ_PUSH_CFG(2, float, true, 1, 5, 3)
-WQ_PUSH_CFG(3, float, false, 1, 7, 8)
-WQ_PUSH_CFG(3, float, true, 1, 7, 2)
-WQ_PUSH_CFG(4, float, false, 1, 5, 8)
-WQ_PUSH_CFG(4, float, true, 1, 5, 3)
-WQ_PUSH_CFG(5, float, false, 2, 11, 4)
-WQ_PUSH_CFG(5, float, true, 2, 11, 2)
-WQ_PUSH_CFG(6, float, false, 3, 13, 8)
-WQ_PUSH_CFG(6, float, true, 3, 13, 2)
+#define WQ_PUSH_CFG(P_, T_, S_, NW_, J3_, C_, WPE_) \
+  template <> struct PushCfg<P_, T_, S_> { static constexpr int NW = NW_, J3 = J3_, C = C_, WPE = WPE_; };
+WQ_PUSH_CFG(2, double, false, 1, 5, 4, 0)
+WQ_PUSH_CFG(2, double, true, 1, 5, 3, 0)
+WQ_PUSH_CFG(3, double, false, 1, 7, 4, 0)
+WQ_PUSH_CFG(3, double, true, 1, 7, 2, 0)
+WQ_PUSH_CFG(4, double, false, 1, 5, 4, 0)
+WQ_PUSH_CFG(4, double, true, 2, 9, 3, 3)
+WQ_PUSH_CFG(5, double, false, 2, 11, 4, 0)
+WQ_PUSH_CFG(5, double, true, 2, 11, 2, 0)
+WQ_PUSH_CFG(6, double, false, 1, 4, 8, 0)
+WQ_PUSH_CFG(6, double, true, 4, 13, 3, 0)
+WQ_PUSH_CFG(2, float, false, 1, 5, 8, 0)
+WQ_PUSH_CFG(2, float, true, 1, 5, 3, 0)
+WQ_PUSH_CFG(3, float, false, 1, 7, 8, 0)
+WQ_PUSH_CFG(3, float, true, 1, 7, 2, 0)
+WQ_PUSH_CFG(4, float, false, 1, 5, 8, 0)
+WQ_PUSH_CFG(4, float, true, 2, 9, 3, 0)
+WQ_PUSH_CFG(5, float, false, 2, 11, 4, 0)
+WQ_PUSH_CFG(5, float, true, 2, 11, 2, 0)
+WQ_PUSH_CFG(6, float, false, 3, 13, 8, 0)
+WQ_PUSH_CFG(6, float, true, 3, 13, 3, 0)
 #undef WQ_PUSH_CFG
 
 template <int P, typename T, bool STIFF>
@@ -96,7 +97,13 @@ struct Shape {
   static constexpr size_t HBUF = size_t(C) * NH * QC * J3;
   static constexpr size_t GBUF = size_t(C) * NG * IC * J3;
   static constexpr size_t STAGE = size_t(J3) * IC * IC;
-  static constexpr size_t LDS_BYTES = (HBUF + GBUF + STAGE) * sizeof(T);
+  // For the stiffness, whose H buffer is large, the row stage shares it: H
+  // is dead from the end of phase B to the merge of the next chunk, which is
+  // where rows are stored.
+  static constexpr bool STAGE_IN_H = STIFF;
+  static constexpr size_t HSBUF = STAGE_IN_H ? (HBUF > STAGE ? HBUF : STAGE) : HBUF;
+  static constexpr size_t SBUF = STAGE_IN_H ? 1 : STAGE;
+  static constexpr size_t LDS_BYTES = (HSBUF + GBUF + (STAGE_IN_H ? 0 : STAGE)) * sizeof(T);
   static_assert(IC * J3 <= NT, "one phase-C item per lane");
   static_assert(LDS_BYTES <= 64 * 1024, "LDS budget per workgroup");
 };
@@ -217,13 +224,14 @@ __global__ __launch_bounds__(256) void k_first(PlanView v) {
 }
 
 template <int P, typename T, bool STIFF>
-__global__ __launch_bounds__((Shape<P, T, STIFF>::NT)) void k_push(PlanView v, T* __restrict__ out, int nseg) {
+__device__ __forceinline__ void push_body(PlanView v, T* __restrict__ out, int nseg) {
   using S = Shape<P, T, STIFF>;
   constexpr int IC = S::IC, QC = S::QC, C = S::C, NT = S::NT, J3 = S::J3;
   constexpr int NG = S::NG, NH = S::NH, NCT = S::NCT;
-  __shared__ __align__(16) T hbuf[S::HBUF];     // [C][NH][QC][J3]   (c, h, qq2, u)
+  __shared__ __align__(16) T hbuf[S::HSBUF];    // [C][NH][QC][J3]   (c, h, qq2, u)
   __shared__ __align__(16) T gbuf[S::GBUF];     // [C][NG][IC][J3]   (c, g, jj2, u)
-  __shared__ __align__(16) T stage[S::STAGE];   // one row: [u3][jj2][jj1]
+  __shared__ __align__(16) T sbuf[S::SBUF];
+  T* const stage = S::STAGE_IN_H ? hbuf : sbuf;  // one row: [u3][jj2][jj1]
 
   const DirView d1 = v.dir[0], d2 = v.dir[1], d3 = v.dir[2];
   const int n1 = d1.n, n2 = d2.n, nq1 = d1.nq, nq2 = d2.nq, nel1 = d1.nel;
@@ -443,6 +451,19 @@ __global__ __launch_bounds__((Shape<P, T, STIFF>::NT)) void k_push(PlanView v, T
   for (int s = 0; s <= P; ++s) flush(e_cur + s);
 }
 
+
+// The pencil kernel; configurations with WPE > 0 use the variant whose
+// register allocation is bounded for that many waves per SIMD.
+template <int P, typename T, bool STIFF>
+__global__ __launch_bounds__((Shape<P, T, STIFF>::NT)) void k_push(PlanView v, T* __restrict__ out, int nseg) {
+  push_body<P, T, STIFF>(v, out, nseg);
+}
+template <int P, typename T, bool STIFF>
+__global__ __launch_bounds__((Shape<P, T, STIFF>::NT))
+__attribute__((amdgpu_waves_per_eu(PushCfg<P, T, STIFF>::WPE))) void k_push_wpe(PlanView v, T* __restrict__ out, int nseg) {
+  push_body<P, T, STIFF>(v, out, nseg);
+}
+
 template <int P, typename T, bool STIFF>
 hipError_t push_launch(const PlanView& v, void* out, hipStream_t s) {
   using Sh = Shape<P, T, STIFF>;
@@ -454,7 +475,10 @@ hipError_t push_launch(const PlanView& v, void* out, hipStream_t s) {
   if (items <= 0 || items > INT32_MAX) return hipErrorInvalidConfiguration;
   const int64_t plane = int64_t(v.dir[0].nq) * v.dir[1].nq;
   hipLaunchKernelGGL((k_first<P, T, STIFF>), dim3(unsigned((plane + 255) / 256), unsigned(v.dir[2].n)), dim3(256), 0, s, v);
-  hipLaunchKernelGGL((k_push<P, T, STIFF>), dim3(unsigned(items)), dim3(Sh::NT), 0, s, v, static_cast<T*>(out), nseg);
+  if constexpr (PushCfg<P, T, STIFF>::WPE > 0)
+    hipLaunchKernelGGL((k_push_wpe<P, T, STIFF>), dim3(unsigned(items)), dim3(Sh::NT), 0, s, v, static_cast<T*>(out), nseg);
+  else
+    hipLaunchKernelGGL((k_push<P, T, STIFF>), dim3(unsigned(items)), dim3(Sh::NT), 0, s, v, static_cast<T*>(out), nseg);
   return hipGetLastError();
 }
 
