@@ -66,9 +66,9 @@ WQ_PUSH_CFG(2, double, false, 1, 5, 4, 0)
 WQ_PUSH_CFG(2, double, true, 1, 5, 3, 0)
 WQ_PUSH_CFG(3, double, false, 1, 7, 4, 0)
 WQ_PUSH_CFG(3, double, true, 1, 7, 2, 0)
-WQ_PUSH_CFG(4, double, false, 1, 5, 4, 0)
+WQ_PUSH_CFG(4, double, false, 1, 5, 6, 0)
 WQ_PUSH_CFG(4, double, true, 2, 9, 3, 3)
-WQ_PUSH_CFG(5, double, false, 2, 11, 4, 0)
+WQ_PUSH_CFG(5, double, false, 2, 11, 2, 0)
 WQ_PUSH_CFG(5, double, true, 2, 11, 2, 0)
 WQ_PUSH_CFG(6, double, false, 1, 4, 8, 0)
 WQ_PUSH_CFG(6, double, true, 4, 13, 3, 0)
