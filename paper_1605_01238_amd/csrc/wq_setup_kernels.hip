@@ -501,6 +501,14 @@ __global__ __launch_bounds__(256) void k_xphys(PlanView v, double* __restrict__ 
   for (int a = 0; a < 3; ++a) xphys[q * 3 + a] = F[a];
 }
 
+// t / d for 0 <= t < 2^20, d >= 1: a float estimate within one of the
+// quotient, then one correction
+__device__ inline int div_small(int t, int d, float inv) {
+  const int q = int(float(t) * inv);
+  const int r = t - q * d;
+  return r < 0 ? q - 1 : (r >= d ? q + 1 : q);
+}
+
 // ---------------------------------------------------------------------------
 // CSR pattern: one wavefront per row.  A row's columns are (j3, j2, j1)
 // lexicographic.  Lanes write 16-byte groups of 4 consecutive entries (the
@@ -509,7 +517,8 @@ __global__ __launch_bounds__(256) void k_xphys(PlanView v, double* __restrict__ 
 __global__ __launch_bounds__(256) void k_pattern(PlanView v, int64_t* __restrict__ row_ptr,
                                                  int32_t* __restrict__ col_idx) {
   const int lane = threadIdx.x & 63;
-  const int64_t row = int64_t(blockIdx.x) * 4 + (threadIdx.x >> 6);
+  // one row per wavefront: the row and everything derived from it are uniform
+  const int64_t row = int64_t(blockIdx.x) * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const DirView d1 = v.dir[0], d2 = v.dir[1], d3 = v.dir[2];
   const int n1 = d1.n, n2 = d2.n, n3 = d3.n;
   const int64_t nrows = int64_t(n1) * n2 * n3;
@@ -528,9 +537,17 @@ __global__ __launch_bounds__(256) void k_pattern(PlanView v, int64_t* __restrict
   }
   const int n12 = n1 * n2;
   const int base = is1 + n1 * is2 + n12 * is3;
-  // column of entry t of the row
+  const float invp = 1.0f / float(plane), inv1 = 1.0f / float(ic1);
+  // entry t of the row -> (jj3, jj2, jj1), t < (2p+1)^3
+  auto split = [&](int t, int& jj3, int& jj2, int& jj1) {
+    jj3 = div_small(t, plane, invp);
+    const int r = t - jj3 * plane;
+    jj2 = div_small(r, ic1, inv1);
+    jj1 = r - jj2 * ic1;
+  };
   auto col_of = [&](int t) {
-    const int jj3 = t / plane, r = t - jj3 * plane, jj2 = r / ic1, jj1 = r - jj2 * ic1;
+    int jj3, jj2, jj1;
+    split(t, jj3, jj2, jj1);
     return base + jj1 + n1 * jj2 + n12 * jj3;
   };
   const int head = min(len, int((4 - (start & 3)) & 3));   // entries before the first boundary
@@ -538,23 +555,38 @@ __global__ __launch_bounds__(256) void k_pattern(PlanView v, int64_t* __restrict
   if (lane < head) col_idx[start + lane] = col_of(lane);
   const int tail0 = head + 4 * ngroups;
   if (lane < len - tail0) col_idx[start + tail0 + lane] = col_of(tail0 + lane);
+  // 16-byte groups: lane takes groups lane, lane+64, ...; its position moves
+  // by 256 entries per step, (s3, s2, s1) in the row's mixed radix
+  const int s3 = 256 / plane, s2 = (256 - s3 * plane) / ic1, s1 = 256 - s3 * plane - s2 * ic1;
+  int jj3, jj2, jj1;
+  split(head + 4 * lane, jj3, jj2, jj1);
   int4* __restrict__ o = reinterpret_cast<int4*>(col_idx + start + head);
   for (int g = lane; g < ngroups; g += 64) {
-    const int t = head + 4 * g;
-    int jj3 = t / plane, r = t - jj3 * plane, jj2 = r / ic1, jj1 = r - jj2 * ic1;
     int c[4];
+    int a1 = jj1, a2 = jj2, a3 = jj3;
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
-      c[k] = base + jj1 + n1 * jj2 + n12 * jj3;
-      if (++jj1 == ic1) {
-        jj1 = 0;
-        if (++jj2 == ic2) {
-          jj2 = 0;
-          ++jj3;
+      c[k] = base + a1 + n1 * a2 + n12 * a3;
+      if (++a1 == ic1) {
+        a1 = 0;
+        if (++a2 == ic2) {
+          a2 = 0;
+          ++a3;
         }
       }
     }
     o[g] = int4{c[0], c[1], c[2], c[3]};
+    jj1 += s1;
+    if (jj1 >= ic1) {
+      jj1 -= ic1;
+      ++jj2;
+    }
+    jj2 += s2;
+    if (jj2 >= ic2) {
+      jj2 -= ic2;
+      ++jj3;
+    }
+    jj3 += s3;
   }
 }
 
