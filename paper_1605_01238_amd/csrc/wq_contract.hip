@@ -176,20 +176,28 @@ __device__ inline void store_vec(T* __restrict__ p, const T (&v)[NV]) {
 //  K13 T^(0,1), K23 T^(1,0), K23 T^(0,1)) or the single det J T^(0,0) of
 // the mass.  Lanes run over the (q2, q1) plane, whose points are contiguous
 // in the field, so every load is coalesced; the record of a point,
-// [jj3][c], is stored contiguously for the pencil kernel.
+// [jj3][c], is stored contiguously for the pencil kernel.  The 64 records of
+// a wavefront are one contiguous stretch of Y; they pass through LDS so that
+// consecutive lanes store consecutive elements (whole lines per store).
 template <int P, typename T, bool STIFF>
 __global__ __launch_bounds__(256) void k_first(PlanView v) {
   constexpr int IC = 2 * P + 1, QC = 3 * P + 1, NCH = STIFF ? kYChannels : 1;
+  constexpr int REC = IC * NCH;                           // elements per record
+  constexpr int LPR = (9216 / int(sizeof(T) * REC)) < 64 ? (9216 / int(sizeof(T) * REC)) : 64;   // records per round
+  __shared__ __align__(16) T stg[4][LPR * REC];
   const DirView d1 = v.dir[0], d2 = v.dir[1], d3 = v.dir[2];
   const int64_t plane = int64_t(d1.nq) * d2.nq;
-  const int64_t l = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  const int tid = threadIdx.x, wv = tid / 64, ln = tid % 64;
+  const int64_t l0 = int64_t(blockIdx.x) * blockDim.x + wv * 64;   // first point of the wave
+  const int64_t l = l0 + ln;
   const int i3 = blockIdx.y;
-  if (l >= plane) return;
+  if (l0 >= plane) return;   // uniform per wave
+  const bool valid = l < plane;
   int qs3, qc3;
   q_range(i3, P, d3.nel, qs3, qc3);
   const T* __restrict__ T3 = op_t<T>(d3) + size_t(i3) * QC * IC * 4;    // [qq3][jj3][o]
   const int64_t N = v.nqtot;
-  const T* __restrict__ f = static_cast<const T*>(v.field) + l + plane * qs3;
+  const T* __restrict__ f = static_cast<const T*>(v.field) + (valid ? l : l0) + plane * qs3;
   T acc[IC * NCH];
 #pragma unroll
   for (int k = 0; k < IC * NCH; ++k) acc[k] = T(0);
@@ -219,8 +227,22 @@ __global__ __launch_bounds__(256) void k_first(PlanView v) {
       for (int jj = 0; jj < IC; ++jj) acc[jj] += t[jj * 4 + R00] * k0;
     }
   }
-  T* y = static_cast<T*>(v.ybuf) + (int64_t(i3) * plane + l) * (IC * NCH);
-  store_vec<T, IC * NCH>(y, acc);
+  // the wave's records are contiguous in Y: pass them through LDS in rounds
+  // of LPR records so that consecutive lanes store consecutive elements
+  const int nvalid = int(plane - l0 < 64 ? plane - l0 : 64);
+  T* y = static_cast<T*>(v.ybuf) + (int64_t(i3) * plane + l0) * REC;
+  T* st = stg[wv];
+  for (int r0 = 0; r0 < nvalid; r0 += LPR) {
+    if (ln >= r0 && ln < r0 + LPR) store_vec<T, REC>(st + (ln - r0) * REC, acc);
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    const int n = (nvalid - r0 < LPR ? nvalid - r0 : LPR) * REC;
+    for (int e = ln; e < n; e += 64) y[int64_t(r0) * REC + e] = st[e];
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  }
 }
 
 template <int P, typename T, bool STIFF>
