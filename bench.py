@@ -94,8 +94,8 @@ def main():
     args = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; rows shard without "
-                          "communication (see DESIGN.md), but no multi-GPU path is built",
+        print(json.dumps({"error": "one GPU only: rows would shard across GPUs without "
+                          "communication, but no multi-GPU path is built",
                           "n_gpus": args.gpus}))
         sys.exit(2)
     import torch
@@ -140,11 +140,17 @@ def main():
         step()
     plan.sync()
     torch.cuda.synchronize()
+    # throughput: K plain steps between two synchronizations
     t0 = time.perf_counter()
+    for i in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    plan.sync()
+    # per-step latency: K more steps, each bracketed by events on the stream
     for i in range(args.steps):
         step(i)
     torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
     plan.sync()
 
     n_mat = len(which_names)

@@ -76,7 +76,7 @@ typedef enum {
 enum { WQ_MASS = 1, WQ_STIFF = 2 };
 enum { WQ_FP64 = 0, WQ_FP32 = 1 };
 
-/* Limits of this build. */
+/* Degrees the library is compiled for (kernels are instantiated per degree). */
 #define WQ_MIN_P 2
 #define WQ_MAX_P 6
 
