@@ -207,55 +207,61 @@ __global__ __launch_bounds__(256) void k_rules(PlanView v) {
       }
     }
   }
-  // Gauss-Legendre nodes/weights on [-1, 1]: Newton's method on the
-  // Legendre polynomial P_NG, in FP64 to convergence, then in double-double.
-  if (tid >= 64 && tid < 64 + NG) {
-    const int t = tid - 64;
-    double z = cos(M_PI * (t + 0.75) / (NG + 0.5));
-    for (int it = 0; it < 100; ++it) {
-      double p0 = 1.0, p1 = z;
-      for (int k = 2; k <= NG; ++k) {
-        const double p2 = ((2 * k - 1) * z * p1 - (k - 1) * p0) / k;
-        p0 = p1;
-        p1 = p2;
-      }
-      const double dz = p1 / (NG * (z * p1 - p0) / (z * z - 1.0));
-      z -= dz;
-      if (fabs(dz) <= 1e-15) break;
-    }
-    dd zz = dd_from(z), dp{0.0, 0.0};
-    for (int it = 0; it < 3; ++it) {
-      dd p0 = dd_from(1.0), p1 = zz;
-      for (int k = 2; k <= NG; ++k) {
-        const dd p2 = ((zz * p1) * double(2 * k - 1) - p0 * double(k - 1)) / double(k);
-        p0 = p1;
-        p1 = p2;
-      }
-      dp = ((zz * p1 - p0) * double(NG)) / (zz * zz - 1.0);
-      if (it < 2) zz = zz - p1 / dp;
-    }
-    gx[t] = zz;
-    gw[t] = 2.0 / ((1.0 - zz * zz) * (dp * dp));
-  }
-  __syncthreads();
-  // B-splines at the Gauss points of the knot-spans supporting B_i.
+  // Wave 1 forms the Gauss-Legendre rule and the B-splines at the Gauss
+  // points of the knot-spans supporting B_i, while wave 0 builds A.
+  // Nodes/weights on [-1, 1]: Newton's method on the Legendre polynomial
+  // P_NG, in FP64 to convergence, then in double-double.
   const int e0 = i - P > 0 ? i - P : 0;
   const int e1 = i + 1 < nel ? i + 1 : nel;
   const int ng = (e1 - e0) * NG;
-  for (int g = tid; g < ng; g += 256) {
-    const int e = e0 + g / NG, t = g % NG;
-    const double a = d.knots[e + P], b = d.knots[e + P + 1];
-    const dd half = two_sum(b, -a) * 0.5;
-    const dd xg = two_sum(a, b) * 0.5 + half * gx[t];
-    dd N[P + 1], D[P + 1];
-    basis_funs<P, dd>(d.knots, e + P, xg, N, D);
-#pragma unroll
-    for (int r = 0; r <= P; ++r) {
-      gval[g][r] = N[r];
-      gder[g][r] = D[r];
+  if (wave == 1) {
+    if (lane < NG) {
+      const int t = lane;
+      double z = cos(M_PI * (t + 0.75) / (NG + 0.5));
+      for (int it = 0; it < 100; ++it) {
+        double p0 = 1.0, p1 = z;
+        for (int k = 2; k <= NG; ++k) {
+          const double p2 = ((2 * k - 1) * z * p1 - (k - 1) * p0) / k;
+          p0 = p1;
+          p1 = p2;
+        }
+        const double dz = p1 / (NG * (z * p1 - p0) / (z * z - 1.0));
+        z -= dz;
+        if (fabs(dz) <= 1e-15) break;
+      }
+      dd zz = dd_from(z), dp{0.0, 0.0};
+      for (int it = 0; it < 3; ++it) {
+        dd p0 = dd_from(1.0), p1 = zz;
+        for (int k = 2; k <= NG; ++k) {
+          const dd p2 = ((zz * p1) * double(2 * k - 1) - p0 * double(k - 1)) / double(k);
+          p0 = p1;
+          p1 = p2;
+        }
+        dp = ((zz * p1 - p0) * double(NG)) / (zz * zz - 1.0);
+        if (it < 2) zz = zz - p1 / dp;
+      }
+      gx[t] = zz;
+      gw[t] = 2.0 / ((1.0 - zz * zz) * (dp * dp));
     }
-    gwt[g] = half * gw[t];
-    gspan[g] = e;
+    // the nodes were written by other lanes of this wavefront
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    for (int g = lane; g < ng; g += 64) {
+      const int e = e0 + g / NG, t = g % NG;
+      const double a = d.knots[e + P], b = d.knots[e + P + 1];
+      const dd half = two_sum(b, -a) * 0.5;
+      const dd xg = two_sum(a, b) * 0.5 + half * gx[t];
+      dd N[P + 1], D[P + 1];
+      basis_funs<P, dd>(d.knots, e + P, xg, N, D);
+#pragma unroll
+      for (int r = 0; r <= P; ++r) {
+        gval[g][r] = N[r];
+        gder[g][r] = D[r];
+      }
+      gwt[g] = half * gw[t];
+      gspan[g] = e;
+    }
   }
   __syncthreads();
   // Exact 1D integrals (degree <= 2p per span, p+1 Gauss points), in dd:
@@ -341,14 +347,19 @@ __global__ __launch_bounds__(256) void k_rules(PlanView v) {
     // r2 = b - A w (kept equations), r1 = A^T lam - w (this lane)
     double r2[IC];
     dd r1 = -w;
-    // all IC rows (zero beyond #I_i; a dropped row is computed and unused,
-    // its multiplier stays 0), so the IC reductions are independent
+    if (it == 0) {   // from (w, lam) = 0 the residuals are b and 0
 #pragma unroll
-    for (int j = 0; j < IC; ++j) {
-      const dd a = live ? A[al][j][lane] : dd{0.0, 0.0};
-      const dd s = dd_wave_sum(a * w);
-      r2[j] = dd_to_double(bvec[pair][j] - s);
-      r1 += a * lam[j];
+      for (int j = 0; j < IC; ++j) r2[j] = dd_to_double(bvec[pair][j]);
+    } else {
+      // all IC rows (zero beyond #I_i; a dropped row is computed and unused,
+      // its multiplier stays 0), so the IC reductions are independent
+#pragma unroll
+      for (int j = 0; j < IC; ++j) {
+        const dd a = live ? A[al][j][lane] : dd{0.0, 0.0};
+        const dd s = dd_wave_sum(a * w);
+        r2[j] = dd_to_double(bvec[pair][j] - s);
+        r1 += a * lam[j];
+      }
     }
     // t = (Q^T r1)[0:r]: apply H_0 .. H_{r-1}
     double u = live ? dd_to_double(r1) : 0.0;
