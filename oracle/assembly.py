@@ -23,6 +23,9 @@ and no boundary conditions.
   Section 1) with p+1 Gauss-Legendre points per direction and element; exact
   for affine maps and constant coefficients, used by the exactness pins.
 
+The same definitions in d = 2 (two directions, d^2 = 4 stiffness terms) are
+taken when two knot vectors are given.
+
 Pins (tests/test_oracle_assembly.py): direct == sum-factorized (the identity
 between eq:massquadrature and eq:sumfactorization), affine exactness against
 a closed Kronecker formula of exact 1D integrals and against SGQ, S 1 = 0,
@@ -34,7 +37,8 @@ from typing import Callable, Optional, Sequence
 
 import numpy as np
 
-from .geometry import coefficients_from_jacobian, map_and_jacobian
+from .geometry import (coefficients_from_jacobian, coefficients_from_jacobian_2d, map_and_jacobian,
+                       map_and_jacobian_2d)
 from .rules import rules_for
 
 
@@ -44,36 +48,56 @@ def mode_product(X: np.ndarray, A: np.ndarray, m: int) -> np.ndarray:
 
 
 class Problem:
-    """One 3D single-patch problem: knots, degree, control net, coefficient."""
+    """One single-patch problem in d = 3 (or d = 2) dimensions: knots,
+    degree, control net, coefficient."""
 
     def __init__(self, knots3: Sequence, p: int, ctrl: np.ndarray,
                  coef: Optional[Callable[[np.ndarray], np.ndarray]] = None):
-        if len(knots3) != 3:
-            raise ValueError("3D problems only")
+        d = len(knots3)
+        if d not in (2, 3):
+            raise ValueError("2D or 3D problems only")
+        self.d = d
         self.p = p
         self.knots3 = [np.asarray(k, dtype=np.float64) for k in knots3]
         self.rules = [rules_for(list(k), p) for k in self.knots3]
         self.n = tuple(r.n for r in self.rules)
         self.ctrl = np.asarray(ctrl, dtype=np.float64)
-        if self.ctrl.shape != (self.n[2], self.n[1], self.n[0], 3):
-            raise ValueError("control net shape must be (n3, n2, n1, 3)")
+        if self.ctrl.shape != tuple(reversed(self.n)) + (d,):
+            raise ValueError("control net shape must be (n_d, ..., n1, d)")
         self.coef = coef
         self.B = [(r.table64(0), r.table64(1)) for r in self.rules]
 
     # ---- indices ---------------------------------------------------------
     def multi(self, row: int):
-        n1, n2, _ = self.n
-        return row % n1, (row // n1) % n2, row // (n1 * n2)
+        out = []
+        for nk in self.n:
+            out.append(row % nk)
+            row //= nk
+        return tuple(out)
+
+    def linear(self, idx) -> int:
+        r, s = 0, 1
+        for k, nk in enumerate(self.n):
+            r += idx[k] * s
+            s *= nk
+        return r
 
     def row_columns(self, row: int) -> np.ndarray:
         i = self.multi(row)
-        I = [self.rules[k].I[i[k]] for k in range(3)]
-        n1, n2, _ = self.n
-        return np.array([j1 + n1 * (j2 + n2 * j3) for j3 in I[2] for j2 in I[1] for j1 in I[0]],
-                        dtype=np.int64)
+        I = [self.rules[k].I[i[k]] for k in range(self.d)]
+        # direction 1 fastest: iterate the last direction outermost
+        cols = [0]
+        stride = 1
+        strides = []
+        for nk in self.n:
+            strides.append(stride)
+            stride *= nk
+        for k in reversed(range(self.d)):
+            cols = [c + j * strides[k] for c in cols for j in I[k]]
+        return np.array(cols, dtype=np.int64)
 
     def csr_pattern(self):
-        N = self.n[0] * self.n[1] * self.n[2]
+        N = int(np.prod(self.n))
         cols = [self.row_columns(r) for r in range(N)]
         row_ptr = np.zeros(N + 1, dtype=np.int64)
         row_ptr[1:] = np.cumsum([len(c) for c in cols])
@@ -89,20 +113,29 @@ class Problem:
 
     GRID_LIMIT = 100_000   # quadrature grids up to this size are evaluated once
 
+    def _geometry(self, X):
+        if self.d == 3:
+            return map_and_jacobian(self.knots3, self.p, self.ctrl, X[0], X[1], X[2])
+        return map_and_jacobian_2d(self.knots3, self.p, self.ctrl, X[0], X[1])
+
+    def _coefficients(self, J, a):
+        return coefficients_from_jacobian(J, a) if self.d == 3 else coefficients_from_jacobian_2d(J, a)
+
     def _fields_on(self, X):
-        F, J = map_and_jacobian(self.knots3, self.p, self.ctrl, X[0], X[1], X[2])
+        F, J = self._geometry(X)
         F = F.astype(np.float64)
-        a = None if self.coef is None else self.coef(F.reshape(-1, 3)).reshape(F.shape[:3])
-        det, K = coefficients_from_jacobian(J, a)
+        d = self.d
+        a = None if self.coef is None else self.coef(F.reshape(-1, d)).reshape(F.shape[:d])
+        det, K = self._coefficients(J, a)
         return det.astype(np.float64), K.astype(np.float64), F
 
     def row_fields(self, row: int):
-        """Coefficients on the block Q_i1 x Q_i2 x Q_i3 (arrays indexed
-        [q1, q2, q3]): mass factor det J, stiffness K (3x3), and F, evaluated
-        at the exact quadrature points (on the whole grid at once when it is
-        small, else on the row's block)."""
+        """Coefficients on the block Q_i1 x ... x Q_id (arrays indexed
+        [q1, ..., qd]): mass factor det J, stiffness K (d x d), and F,
+        evaluated at the exact quadrature points (on the whole grid at once
+        when it is small, else on the row's block)."""
         i = self.multi(row)
-        Q = [self.rules[k].Q[i[k]] for k in range(3)]
+        Q = [self.rules[k].Q[i[k]] for k in range(self.d)]
         last = getattr(self, "_last", None)
         if last is not None and last[0] == row:
             return last[1]
@@ -112,53 +145,58 @@ class Problem:
             det, K, F = self._grid
             s = tuple(slice(q[0], q[-1] + 1) for q in Q)
             return det[s], K[s], F[s]
-        out = self._fields_on([[self.rules[k].x[q] for q in Q[k]] for k in range(3)])
+        out = self._fields_on([[self.rules[k].x[q] for q in Q[k]] for k in range(self.d)])
         self._last = (row, out)
         return out
 
     # ---- formation ---------------------------------------------------------
     def row(self, row: int, which: str, method: str = "sumfact") -> np.ndarray:
         """Values of the row in increasing column order."""
+        d = self.d
         i = self.multi(row)
         det, K, _ = self.row_fields(row)
         if which == "mass":
-            terms = [((0, 0, 0), (0, 0, 0), det)]
+            terms = [((0,) * d, (0,) * d, det)]
         elif which == "stiff":
             terms = []
-            for l in range(3):          # test-function derivative direction
-                for m in range(3):      # trial-function derivative direction
-                    al = tuple(int(k == m) for k in range(3))
-                    be = tuple(int(k == l) for k in range(3))
+            for l in range(d):          # test-function derivative direction
+                for m in range(d):      # trial-function derivative direction
+                    al = tuple(int(k == m) for k in range(d))
+                    be = tuple(int(k == l) for k in range(d))
                     terms.append((al, be, K[..., l, m]))
         else:
             raise ValueError(which)
         out = None
         for al, be, field in terms:
-            T = [self.operator(k, i[k], al[k], be[k]) for k in range(3)]
+            T = [self.operator(k, i[k], al[k], be[k]) for k in range(d)]
             if method == "direct":
-                v = np.einsum("ax,by,cz,xyz->abc", T[0], T[1], T[2], field, optimize=False)
+                if d == 3:
+                    v = np.einsum("ax,by,cz,xyz->abc", T[0], T[1], T[2], field, optimize=False)
+                else:
+                    v = np.einsum("ax,by,xy->ab", T[0], T[1], field, optimize=False)
             elif method == "sumfact":
                 v = field
-                for k in (2, 1, 0):
+                for k in reversed(range(d)):
                     v = mode_product(v, T[k], k)
             else:
                 raise ValueError(method)
             out = v if out is None else out + v
-        # [j1, j2, j3] -> increasing linear column order (j1 fastest)
-        return np.ascontiguousarray(out.transpose(2, 1, 0)).ravel()
+        # [j1, ..., jd] -> increasing linear column order (j1 fastest)
+        return np.ascontiguousarray(out.transpose(tuple(reversed(range(d))))).ravel()
 
     def assemble(self, which: str, method: str = "sumfact") -> np.ndarray:
-        N = self.n[0] * self.n[1] * self.n[2]
+        N = int(np.prod(self.n))
         return np.concatenate([self.row(r, which, method) for r in range(N)])
 
     # ---- element-wise standard Gauss quadrature (SGQ) -------------------
     def sgq_matrices(self, which: str, n_gauss: Optional[int] = None) -> np.ndarray:
         """Dense N x N Galerkin matrix by element-wise Gauss-Legendre quadrature
         with n_gauss (default p+1) points per direction per element."""
+        d = self.d
         ng = self.p + 1 if n_gauss is None else n_gauss
         gx, gw = np.polynomial.legendre.leggauss(ng)
         pts, wts = [], []
-        for k in range(3):
+        for k in range(d):
             chi = np.unique(self.knots3[k])
             P, W = [], []
             for e in range(len(chi) - 1):
@@ -167,33 +205,38 @@ class Problem:
                 W.append(0.5 * (b - a) * gw)
             pts.append(np.concatenate(P))
             wts.append(np.concatenate(W))
-        F, J = map_and_jacobian(self.knots3, self.p, self.ctrl, pts[0], pts[1], pts[2])
+        F, J = self._geometry(pts)
         F = F.astype(np.float64)
-        a = None if self.coef is None else self.coef(F.reshape(-1, 3)).reshape(F.shape[:3])
-        det, K = coefficients_from_jacobian(J, a)
+        a = None if self.coef is None else self.coef(F.reshape(-1, d)).reshape(F.shape[:d])
+        det, K = self._coefficients(J, a)
         det, K = det.astype(np.float64), K.astype(np.float64)
-        Wq = wts[0][:, None, None] * wts[1][None, :, None] * wts[2][None, None, :]
+        if d == 3:
+            Wq = wts[0][:, None, None] * wts[1][None, :, None] * wts[2][None, None, :]
+        else:
+            Wq = wts[0][:, None] * wts[1][None, :]
         # dense basis tables at Gauss points
         from .splines import basis_and_derivs
         tabs = []
-        for k in range(3):
+        for k in range(d):
             V = np.array([basis_and_derivs(list(self.knots3[k]), self.p, float(x))[0] for x in pts[k]])
             D = np.array([basis_and_derivs(list(self.knots3[k]), self.p, float(x))[1] for x in pts[k]])
             tabs.append((V.T, D.T))   # (n_k, n_gauss_total)
-        n1, n2, n3 = self.n
-        N = n1 * n2 * n3
+        N = int(np.prod(self.n))
 
         def phi(dirs_deriv):
             # values of all N tensor basis functions at all points, flattened
-            A = [tabs[k][dirs_deriv[k]] for k in range(3)]
-            T = np.einsum("ix,jy,kz->kjixyz", A[0], A[1], A[2])
+            A = [tabs[k][dirs_deriv[k]] for k in range(d)]
+            if d == 3:
+                T = np.einsum("ix,jy,kz->kjixyz", A[0], A[1], A[2])
+            else:
+                T = np.einsum("ix,jy->jixy", A[0], A[1])
             return T.reshape(N, -1)
         if which == "mass":
-            P0 = phi((0, 0, 0))
+            P0 = phi((0,) * d)
             return (P0 * (Wq * det).ravel()[None, :]) @ P0.T
-        G = [phi(tuple(int(k == d) for k in range(3))) for d in range(3)]
+        G = [phi(tuple(int(k == dd) for k in range(d))) for dd in range(d)]
         S = np.zeros((N, N))
-        for l in range(3):
-            for m in range(3):
+        for l in range(d):
+            for m in range(d):
                 S += (G[l] * (Wq * K[..., l, m]).ravel()[None, :]) @ G[m].T
         return S

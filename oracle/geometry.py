@@ -18,10 +18,14 @@ a reference, the oracle evaluates the same sums in x87 extended precision
 points) the univariate B-spline values and derivatives are exact rationals
 before conversion.  Results are rounded to FP64 by the callers.
 
+The 2D forms (``map_and_jacobian_2d``, ``coefficients_from_jacobian_2d``)
+follow the same definitions with (p+1)^2 functions per point and a 2x2 J.
+
 Pins (tests/test_oracle_geometry.py): Greville control points give the
 identity map (J = I, K = I); an affine control net gives J = A everywhere;
 J agrees with central finite differences of F; K agrees with an
-independently computed det(J) inv(J) inv(J)^T (numpy.linalg).
+independently computed det(J) inv(J) inv(J)^T (numpy.linalg); the same for
+the 2D forms.
 """
 from __future__ import annotations
 
@@ -124,6 +128,43 @@ def coefficients_from_jacobian(J: np.ndarray, a: Optional[np.ndarray] = None):
     adj = np.stack([np.stack([c00, c10, c20], -1),
                     np.stack([c01, c11, c21], -1),
                     np.stack([c02, c12, c22], -1)], -2)
+    K = np.einsum("...ik,...jk->...ij", adj, adj) / det[..., None, None]
+    if a is not None:
+        K = K * np.asarray(a)[..., None, None]
+    return det, K
+
+
+def map_and_jacobian_2d(knots2, p: int, ctrl: np.ndarray, X1, X2):
+    """F and J = dF/dzeta of a bivariate map on the grid X1 x X2.
+
+    ctrl: (n2, n1, 2) control points (linear index i1 + n1 i2).  Returns F
+    with shape (len(X1), len(X2), 2) and J with shape (len(X1), len(X2), 2, 2),
+    J[..., a, b] = dF_a / dzeta_b, in longdouble."""
+    ctrl = np.asarray(ctrl).astype(LD)
+    f1, V1, D1 = local_basis(knots2[0], p, X1)
+    f2, V2, D2 = local_basis(knots2[1], p, X2)
+    r = np.arange(p + 1)
+    i1 = f1[:, None] + r[None, :]              # (n1, p+1)
+    i2 = f2[:, None] + r[None, :]
+    # Cloc[a, b, l2, l1, :] = ctrl[i2[b, l2], i1[a, l1], :]
+    Cloc = ctrl[i2[None, :, :, None], i1[:, None, None, :], :]
+
+    def contract(A1, A2):
+        W = A2[None, :, :, None] * A1[:, None, None, :]
+        return np.einsum("abyz,abyzd->abd", W, Cloc)
+    F = contract(V1, V2)
+    J = np.stack([contract(D1, V2), contract(V1, D2)], axis=-1)
+    return F, J
+
+
+def coefficients_from_jacobian_2d(J: np.ndarray, a: Optional[np.ndarray] = None):
+    """2D forms of eq. mass2 and eq. coef_stiff: c = det J and
+    K = a det(J) J^{-1} J^{-T} = a adj(J) adj(J)^T / det(J) with
+    adj(J) = [[J11, -J01], [-J10, J00]].  Returns (detJ[...], K[..., 2, 2])."""
+    j = J
+    det = j[..., 0, 0] * j[..., 1, 1] - j[..., 0, 1] * j[..., 1, 0]
+    adj = np.stack([np.stack([j[..., 1, 1], -j[..., 0, 1]], -1),
+                    np.stack([-j[..., 1, 0], j[..., 0, 0]], -1)], -2)
     K = np.einsum("...ik,...jk->...ij", adj, adj) / det[..., None, None]
     if a is not None:
         K = K * np.asarray(a)[..., None, None]

@@ -59,19 +59,25 @@ def greville(knots: np.ndarray, p: int) -> np.ndarray:
 def control_net(knots3, p: int, seed: Optional[int], amp_h: float = 0.05,
                 twist_deg: float = 0.0, affine: Optional[np.ndarray] = None,
                 shift: Optional[np.ndarray] = None) -> np.ndarray:
-    """Control net of a trivariate spline map on the given knots.
+    """Control net of a trivariate (or, given two knot vectors, bivariate)
+    spline map on the given knots.
 
     Recipe: Greville points (identity map); optionally an affine map
-    x -> A x + s; optionally a twist of the (x, y) coordinates about the
-    axis (1/2, 1/2, z) by an angle growing linearly in z up to ``twist_deg``
-    degrees at z = 1; then a seeded uniform perturbation U(-amp_h*h, amp_h*h)
-    of every coordinate of every control point, h being the smallest span
-    length.  ``seed=None`` disables the perturbation.
-    Returns float64 of shape (n3, n2, n1, 3)."""
+    x -> A x + s; optionally (3D only) a twist of the (x, y) coordinates
+    about the axis (1/2, 1/2, z) by an angle growing linearly in z up to
+    ``twist_deg`` degrees at z = 1; then a seeded uniform perturbation
+    U(-amp_h*h, amp_h*h) of every coordinate of every control point, h being
+    the smallest span length.  ``seed=None`` disables the perturbation.
+    Returns float64 of shape (n3, n2, n1, 3), or (n2, n1, 2) in 2D."""
     g = [greville(np.asarray(k, dtype=np.float64), p) for k in knots3]
-    n1, n2, n3 = (len(x) for x in g)
-    X3, X2, X1 = np.meshgrid(g[2], g[1], g[0], indexing="ij")
-    P = np.stack([X1, X2, X3], axis=-1).astype(np.float64)
+    if len(g) == 2:
+        if twist_deg:
+            raise ValueError("the twist is defined for 3D nets only")
+        X2, X1 = np.meshgrid(g[1], g[0], indexing="ij")
+        P = np.stack([X1, X2], axis=-1).astype(np.float64)
+    else:
+        X3, X2, X1 = np.meshgrid(g[2], g[1], g[0], indexing="ij")
+        P = np.stack([X1, X2, X3], axis=-1).astype(np.float64)
     if affine is not None:
         A = np.asarray(affine, dtype=np.float64)
         P = P @ A.T
@@ -100,6 +106,8 @@ class CoefficientField:
 
     def __call__(self, x: np.ndarray) -> np.ndarray:
         x = np.asarray(x, dtype=np.float64)
+        if x.shape[-1] == 2:    # a plane domain: the field on z = 0
+            x = np.concatenate([x, np.zeros(x.shape[:-1] + (1,))], axis=-1)
         ph = 2.0 * math.pi * (x @ self.ks.T.astype(np.float64))
         g = np.cos(ph) @ self.alpha + np.sin(ph) @ self.beta
         return 1.0 + 0.5 * np.sin(g)
@@ -117,7 +125,8 @@ def coefficient_field(seed: int) -> CoefficientField:
 
 @dataclasses.dataclass(frozen=True)
 class Workload:
-    """One synthetic single-patch 3D problem."""
+    """One synthetic single-patch problem (3D, or 2D when n_el has two
+    entries)."""
     name: str
     p: int
     n_el: tuple
