@@ -92,7 +92,9 @@ typedef struct {
 
 /*
  * Create a plan (host only; no device work).
- *   d          must be 3.
+ *   d          3, or 2 for a plane patch (Section 3 with two directions);
+ *              a 2D plan reports n[2] = n_qp[2] = 1 and forms the 2D rows,
+ *              of length #I_i1 #I_i2, with the same calls.
  *   p          degree, WQ_MIN_P..WQ_MAX_P; the same in every direction.
  *   n_knots[d] length of each knot vector (n_l + p + 1).
  *   knots[d]   host pointers to FP64 knot vectors: open (first and last
@@ -111,7 +113,7 @@ wq_status wq_plan_create(int d, int p, const int64_t* n_knots, const double* con
 /* Sizes of the problem and of the workspace (host only). */
 wq_status wq_sizes(const wq_plan* plan, wq_sizes_t* out);
 
-/* Parametric quadrature-point coordinates of direction dir (0..2) into the
+/* Parametric quadrature-point coordinates of direction dir (0..d-1) into the
  * host array x_host[n_qp[dir]] (host only; Remark 4.1). */
 wq_status wq_qpoints(const wq_plan* plan, int dir, double* x_host);
 
@@ -134,7 +136,8 @@ wq_status wq_bind(wq_plan* plan, void* workspace, size_t bytes, hipStream_t stre
  *      map F(zeta) = sum_i C_i B_i(zeta), det J, and the coefficient field
  *      (det J; K = a det J J^{-1} J^{-T}) stored in the plan's precision.
  *   ctrl_dev  device FP64 control points, [n3][n2][n1][3] (i1 fastest,
- *             physical x,y,z innermost); copied into the workspace, so the
+ *             physical x,y,z innermost; [n2][n1][2] for d = 2); copied
+ *             into the workspace, so the
  *             caller may free it after the call has completed on stream.
  *   coef_dev  device FP64 array of the diffusion coefficient a at the
  *             quadrature points, [n_qp3][n_qp2][n_qp1] (q1 fastest), or NULL
@@ -154,7 +157,8 @@ wq_status wq_setup(wq_plan* plan, const double* ctrl_dev, const double* coef_dev
 wq_status wq_set_coefficient(wq_plan* plan, const double* coef_dev, hipStream_t stream);
 
 /* Physical quadrature points F(x_q) into x_dev[n_qp3][n_qp2][n_qp1][3]
- * (device FP64), e.g. to sample a coefficient a(x).  Requires wq_setup. */
+ * (x_dev[n_qp2][n_qp1][2] for d = 2; device FP64), e.g. to sample a
+ * coefficient a(x).  Requires wq_setup. */
 wq_status wq_qp_physical(const wq_plan* plan, double* x_dev, hipStream_t stream);
 
 /*

@@ -28,7 +28,8 @@ def _stream(stream) -> Optional[int]:
 
 
 class Plan:
-    """One 3D single-patch problem on the current CUDA (HIP) device."""
+    """One single-patch problem (3D, or 2D given two knot vectors) on the
+    current CUDA (HIP) device."""
 
     def __init__(self, knots3: Sequence[np.ndarray], p: int, precision: int = WQ_FP64):
         self._h = C.c_void_p()
@@ -37,6 +38,7 @@ class Plan:
         n_knots = (C.c_int64 * len(ks))(*[len(k) for k in ks])
         ptrs = (C.POINTER(C.c_double) * len(ks))(*[k.ctypes.data_as(C.POINTER(C.c_double)) for k in ks])
         check(_wq.wq_plan_create(len(ks), p, n_knots, ptrs, precision, C.byref(self._h)))
+        self.d = len(ks)
         self.p = p
         self.precision = precision
         s = _wq.wq_sizes_t()
@@ -68,16 +70,24 @@ class Plan:
         check(_wq.wq_bind(self._h, workspace.data_ptr() + off, workspace.numel() - off, _stream(stream)), self._h)
 
     def setup(self, ctrl, coef=None, stream=None):
-        """ctrl: device float64 tensor (n3, n2, n1, 3); coef: device float64
+        """ctrl: device float64 tensor (n3, n2, n1, 3), or (n2, n1, 2) in 2D;
+        coef: device float64
         tensor with n_qp_total entries (q1 fastest) or None for a = 1."""
+        if ctrl.numel() != self.n_rows * self.d:
+            raise ValueError(f"control net must hold {self.n_rows} x {self.d} values")
+        if coef is not None and coef.numel() != self.n_qp_total:
+            raise ValueError(f"coefficient must hold {self.n_qp_total} values")
         check(_wq.wq_setup(self._h, _ptr(ctrl), _ptr(coef), _stream(stream)), self._h)
 
     def set_coefficient(self, coef, stream=None):
+        if coef is not None and coef.numel() != self.n_qp_total:
+            raise ValueError(f"coefficient must hold {self.n_qp_total} values")
         check(_wq.wq_set_coefficient(self._h, _ptr(coef), _stream(stream)), self._h)
 
     def qp_physical(self, stream=None):
         import torch
-        x = torch.empty((self.n_qp[2], self.n_qp[1], self.n_qp[0], 3), dtype=torch.float64, device="cuda")
+        shape = (self.n_qp[2], self.n_qp[1], self.n_qp[0], 3) if self.d == 3 else (self.n_qp[1], self.n_qp[0], 2)
+        x = torch.empty(shape, dtype=torch.float64, device="cuda")
         check(_wq.wq_qp_physical(self._h, _ptr(x), _stream(stream)), self._h)
         return x
 

@@ -195,6 +195,10 @@ __global__ __launch_bounds__(256) void k_first(PlanView v) {
   const bool valid = l < plane;
   int qs3, qc3;
   q_range(i3, P, d3.nel, qs3, qc3);
+  if (d3.nel == 0) {   // trivial direction of a 2D problem: one point, T3^(0,0) = 1
+    qs3 = 0;
+    qc3 = 1;
+  }
   const T* __restrict__ T3 = op_t<T>(d3) + size_t(i3) * QC * IC * 4;    // [qq3][jj3][o]
   const int64_t N = v.nqtot;
   const T* __restrict__ f = static_cast<const T*>(v.field) + (valid ? l : l0) + plane * qs3;

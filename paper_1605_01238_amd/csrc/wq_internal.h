@@ -88,10 +88,12 @@ struct DirView {
 struct PlanView {
   int p;
   int prec;
+  int d;                 // 3, or 2: then direction 3 is the trivial one (one
+                         // function, one point, nel = 0, operator T^(0,0) = 1)
   DirView dir[3];
   void* field;           // kNumChannels * nqtot in the plan precision
   void* ybuf;            // [n3][nq2][nq1][icap][kYChannels]: field contracted over q3 per test index i3
-  double* ctrl;          // n3*n2*n1*3
+  double* ctrl;          // n3*n2*n1*3 (n2*n1*2 in 2D)
   double* dctrl;         // 3 * n3*n2*n1*3: C_i - C_{i - e_b} along direction b (0 where i_b = 0)
   int32_t* flags;        // kNumFlags
   int64_t nqtot;

@@ -95,6 +95,7 @@ wq::PlanView wq_plan::view() const {
   wq::PlanView v{};
   v.p = p;
   v.prec = prec;
+  v.d = d;
   for (int k = 0; k < 3; ++k) {
     wq::DirView& d = v.dir[k];
     d.n = int(n[k]);
@@ -134,7 +135,7 @@ wq_status wq_plan_create(int d, int p, const int64_t* n_knots, const double* con
                          int precision, wq_plan** out) {
   if (!out) return WQ_EINVAL;
   *out = nullptr;
-  if (d != 3 || p < WQ_MIN_P || p > WQ_MAX_P || !n_knots || !knots) return WQ_EINVAL;
+  if ((d != 2 && d != 3) || p < WQ_MIN_P || p > WQ_MAX_P || !n_knots || !knots) return WQ_EINVAL;
   if (precision != WQ_FP64 && precision != WQ_FP32) return WQ_EINVAL;
   wq_plan* pl = new (std::nothrow) wq_plan();
   if (!pl) return WQ_EINVAL;
@@ -142,7 +143,14 @@ wq_status wq_plan_create(int d, int p, const int64_t* n_knots, const double* con
   pl->p = p;
   pl->prec = precision;
   int64_t nrows = 1, nnz = 1, nqtot = 1;
-  for (int k = 0; k < 3; ++k) {
+  // 2D: direction 3 is trivial (one function, one point; its tables are
+  // constant and written by wq_bind), so the 3D kernels form the 2D rows
+  for (int k = d; k < 3; ++k) {
+    pl->nel[k] = 0;
+    pl->n[k] = 1;
+    pl->nq[k] = 1;
+  }
+  for (int k = 0; k < d; ++k) {
     if (!knots[k] || n_knots[k] <= 0 || n_knots[k] > (int64_t(1) << 24)) { delete pl; return WQ_EINVAL; }
     int64_t nel = 0;
     std::string msg = check_knots(knots[k], n_knots[k], p, &nel);
@@ -180,7 +188,7 @@ wq_status wq_sizes(const wq_plan* plan, wq_sizes_t* out) {
 }
 
 wq_status wq_qpoints(const wq_plan* plan, int dir, double* x) {
-  if (!plan || !x || dir < 0 || dir > 2) return WQ_EINVAL;
+  if (!plan || !x || dir < 0 || dir >= plan->d) return WQ_EINVAL;
   const int p = plan->p;
   const int nel = int(plan->nel[dir]);
   const double* k = plan->knots[dir].data();
@@ -208,10 +216,22 @@ wq_status wq_bind(wq_plan* plan, void* workspace, size_t bytes, hipStream_t stre
   plan->ws_bytes = bytes;
   plan->bound = true;
   plan->setup_done = false;
-  for (int k = 0; k < 3; ++k) {
+  for (int k = 0; k < plan->d; ++k) {
     hipError_t e = hipMemcpyAsync(plan->ws + plan->lay.knots[k], plan->knots[k].data(),
                                   plan->knots[k].size() * 8, hipMemcpyHostToDevice, stream);
     if (e != hipSuccess) return hip_fail(plan, e, "wq_bind: knot upload");
+  }
+  if (plan->d == 2) {   // the trivial direction: qspan = 0, T^(0,0) = 1, other rules 0
+    const int ic = wq::icap_of(plan->p), qc = wq::qcap_of(plan->p);
+    static const double one64 = 1.0;
+    static const float one32 = 1.0f;
+    const wq::Layout& L = plan->lay;
+    hipError_t e = hipMemsetAsync(plan->ws + L.qspan[2], 0, 4, stream);
+    if (e == hipSuccess) e = hipMemsetAsync(plan->ws + L.op64[2], 0, size_t(4) * ic * qc * 8, stream);
+    if (e == hipSuccess) e = hipMemsetAsync(plan->ws + L.op32[2], 0, size_t(4) * ic * qc * 4, stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(plan->ws + L.op64[2], &one64, 8, hipMemcpyHostToDevice, stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(plan->ws + L.op32[2], &one32, 4, hipMemcpyHostToDevice, stream);
+    if (e != hipSuccess) return hip_fail(plan, e, "wq_bind: trivial direction");
   }
   hipError_t e = hipMemsetAsync(plan->ws + plan->lay.flags, 0, wq::kNumFlags * 4, stream);
   if (e != hipSuccess) return hip_fail(plan, e, "wq_bind: flag reset");
@@ -254,7 +274,11 @@ wq_status wq_setup(wq_plan* plan, const double* ctrl_dev, const double* coef_dev
   if (e == hipSuccess) e = hipEventRecord(plan->ev_rules, plan->aux);
   if (e != hipSuccess) return hip_fail(plan, e, "wq_setup: univariate kernel");
   plan->rules_launched = true;
-  e = wq::launch_ctrl_diff(v, ctrl_dev, stream);
+  if (plan->d == 3) {
+    e = wq::launch_ctrl_diff(v, ctrl_dev, stream);
+  } else {   // the 2D geometry reads the plan's copy of the net directly
+    e = hipMemcpyAsync(v.ctrl, ctrl_dev, size_t(plan->nrows) * 2 * 8, hipMemcpyDeviceToDevice, stream);
+  }
   if (e != hipSuccess) return hip_fail(plan, e, "wq_setup: control-net differences");
   e = wq::launch_geometry(v, coef_dev, nullptr, stream);
   if (e != hipSuccess) return hip_fail(plan, e, "wq_setup: geometry kernel");
@@ -299,7 +323,7 @@ wq_status wq_assemble(wq_plan* plan, int which, void* mass, void* stiff, hipStre
 
 wq_status wq_weights(const wq_plan* plan, int dir, int pair, double* w_dev, int32_t* qs_dev,
                      int32_t* qc_dev, hipStream_t stream) {
-  if (!plan || dir < 0 || dir > 2 || pair < 0 || pair > 3 || !w_dev) return WQ_EINVAL;
+  if (!plan || dir < 0 || dir >= plan->d || pair < 0 || pair > 3 || !w_dev) return WQ_EINVAL;
   if (!plan->setup_done) return WQ_ESTATE;
   const int p = plan->p, n = int(plan->n[dir]), qc = wq::qcap_of(p);
   const size_t bytes = size_t(n) * qc * 8;

@@ -722,11 +722,72 @@ __global__ __launch_bounds__(256) void k_geo1(PlanView v, const double* __restri
   f[6 * N + q] = T(s * (c01 * c02 + c11 * c12 + c21 * c22));
 }
 
+// 2D map (d = 2): F, J from the (p+1)^2 control points around each point,
+// the derivative columns through differenced control points as in 3D
+//   J_:,1 = sum (C_i - C_{i - e_1}) g_1(i1) B_2(i2),  J_:,2 = sum (C_i - C_{i - e_2}) B_1(i1) g_2(i2),
+// then det J and K = a adj(J) adj(J)^T / det J with adj(J) = [[J11, -J01], [-J10, J00]]
+// (eqs. mass2 and coef_stiff in two dimensions).  The field keeps the 3D
+// channel order with K33 = K13 = K23 = 0.  With xphys, writes F instead.
+template <int P, typename T>
+__global__ __launch_bounds__(256) void k_geo2d(PlanView v, const double* __restrict__ coef,
+                                               double* __restrict__ xphys) {
+  const int64_t qq = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (qq >= v.nqtot) return;
+  const DirView d1 = v.dir[0], d2 = v.dir[1];
+  const int n1 = d1.n, nq1 = d1.nq;
+  const int q = int(qq), q1 = q % nq1, q2 = q / nq1;
+  const int e1 = d1.qspan[q1], e2 = d2.qspan[q2];
+  double b1[P + 1], b2[P + 1], g1[P + 1], g2[P + 1];
+#pragma unroll
+  for (int l = 0; l <= P; ++l) {
+    b1[l] = d1.bv[q1 * (P + 1) + l];
+    b2[l] = d2.bv[q2 * (P + 1) + l];
+    g1[l] = l ? d1.bw[q1 * P + l - 1] : 0.0;
+    g2[l] = l ? d2.bw[q2 * P + l - 1] : 0.0;
+  }
+  const double* C = v.ctrl;   // [n2][n1][2]
+  double F[2] = {0.0, 0.0}, J[2][2] = {{0.0, 0.0}, {0.0, 0.0}};
+#pragma unroll
+  for (int l2 = 0; l2 <= P; ++l2) {
+#pragma unroll
+    for (int l1 = 0; l1 <= P; ++l1) {
+      const size_t o = (size_t(e2 + l2) * n1 + (e1 + l1)) * 2;
+#pragma unroll
+      for (int a = 0; a < 2; ++a) {
+        const double c = C[o + a];
+        F[a] += c * b1[l1] * b2[l2];
+        if (l1) J[a][0] += (c - C[o - 2 + a]) * g1[l1] * b2[l2];
+        if (l2) J[a][1] += (c - C[o - size_t(n1) * 2 + a]) * b1[l1] * g2[l2];
+      }
+    }
+  }
+  if (xphys) {
+    xphys[size_t(q) * 2 + 0] = F[0];
+    xphys[size_t(q) * 2 + 1] = F[1];
+    return;
+  }
+  const double det = J[0][0] * J[1][1] - J[0][1] * J[1][0];
+  if (!(det > 0.0) || !isfinite(det)) {
+    atomicAdd(&v.flags[FLAG_DETJ_BAD], 1);
+    atomicMin(&v.flags[FLAG_DETJ_FIRST], q);
+  }
+  const double s = (coef ? coef[q] : 1.0) / det;
+  T* f = static_cast<T*>(v.field);
+  const int64_t N = v.nqtot;
+  f[0 * N + q] = T(det);
+  f[1 * N + q] = T(s * (J[1][1] * J[1][1] + J[0][1] * J[0][1]));
+  f[2 * N + q] = T(s * (J[1][0] * J[1][0] + J[0][0] * J[0][0]));
+  f[3 * N + q] = T(0);
+  f[4 * N + q] = T(-s * (J[1][1] * J[1][0] + J[0][1] * J[0][0]));
+  f[5 * N + q] = T(0);
+  f[6 * N + q] = T(0);
+}
+
 template <int P>
 hipError_t points_p(const PlanView& v, hipStream_t s) {
   int maxq = 0;
-  for (int k = 0; k < 3; ++k) maxq = v.dir[k].nq > maxq ? v.dir[k].nq : maxq;
-  dim3 grid((maxq + 255) / 256, 3);
+  for (int k = 0; k < v.d; ++k) maxq = v.dir[k].nq > maxq ? v.dir[k].nq : maxq;
+  dim3 grid((maxq + 255) / 256, v.d);
   hipLaunchKernelGGL(k_points<P>, grid, dim3(256), 0, s, v);
   return hipGetLastError();
 }
@@ -734,14 +795,21 @@ hipError_t points_p(const PlanView& v, hipStream_t s) {
 template <int P>
 hipError_t rules_p(const PlanView& v, hipStream_t s) {
   int maxn = 0;
-  for (int k = 0; k < 3; ++k) maxn = v.dir[k].n > maxn ? v.dir[k].n : maxn;
-  hipLaunchKernelGGL(k_rules<P>, dim3(maxn, 3), dim3(256), 0, s, v);
+  for (int k = 0; k < v.d; ++k) maxn = v.dir[k].n > maxn ? v.dir[k].n : maxn;
+  hipLaunchKernelGGL(k_rules<P>, dim3(maxn, v.d), dim3(256), 0, s, v);
   return hipGetLastError();
 }
 
 template <int P>
 hipError_t geometry_p(const PlanView& v, const double* coef, double* xphys, hipStream_t s) {
   const unsigned blocks = unsigned((v.nqtot + 255) / 256);
+  if (v.d == 2) {
+    if (v.prec == WQ_FP64)
+      hipLaunchKernelGGL((k_geo2d<P, double>), dim3(blocks), dim3(256), 0, s, v, coef, xphys);
+    else
+      hipLaunchKernelGGL((k_geo2d<P, float>), dim3(blocks), dim3(256), 0, s, v, coef, xphys);
+    return hipGetLastError();
+  }
   if (xphys) {
     hipLaunchKernelGGL((k_xphys<P>), dim3(blocks), dim3(256), 0, s, v, xphys);
     return hipGetLastError();

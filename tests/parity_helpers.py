@@ -16,7 +16,7 @@ def gpu_pipeline(knots3, p, ctrl_np, coef=None, which=3, precision=0, stream=Non
     ctrl = torch.from_numpy(np.ascontiguousarray(ctrl_np)).cuda()
     plan.setup(ctrl, None, stream)
     if coef is not None:
-        x = plan.qp_physical(stream).cpu().numpy().reshape(-1, 3)
+        x = plan.qp_physical(stream).cpu().numpy().reshape(-1, plan.d)
         a = torch.from_numpy(np.ascontiguousarray(coef(x))).cuda()
         plan.set_coefficient(a, stream)
     row_ptr, col_idx = plan.pattern(stream=stream)

@@ -32,14 +32,37 @@ def test_exports_every_declared_symbol():
     assert _wq.wq_version().startswith(b"wq-gfx950")
 
 
-def make(knots3, p, prec=0):
+def make(knots3, p, prec=0, d=None):
     from paper_1605_01238_amd import _wq
     ks = [np.ascontiguousarray(k, dtype=np.float64) for k in knots3]
-    n_knots = (C.c_int64 * 3)(*[len(k) for k in ks])
-    ptrs = (C.POINTER(C.c_double) * 3)(*[k.ctypes.data_as(C.POINTER(C.c_double)) for k in ks])
+    n_knots = (C.c_int64 * len(ks))(*[len(k) for k in ks])
+    ptrs = (C.POINTER(C.c_double) * len(ks))(*[k.ctypes.data_as(C.POINTER(C.c_double)) for k in ks])
     h = C.c_void_p()
-    st = _wq.wq_plan_create(3, p, n_knots, ptrs, prec, C.byref(h))
+    st = _wq.wq_plan_create(len(ks) if d is None else d, p, n_knots, ptrs, prec, C.byref(h))
     return st, h
+
+
+@pytest.mark.parametrize("p,nel", [(2, (8, 9)), (4, (32, 17)), (6, (64, 64))])
+def test_sizes_2d(p, nel):
+    """A plane plan: the third direction is the trivial one (one function,
+    one point), so the counts are those of the two real directions."""
+    from paper_1605_01238_amd import _wq
+    from workloads import Workload, open_uniform_knots
+    st, h = make([open_uniform_knots(p, e) for e in nel], p)
+    assert st == 0
+    s = _wq.wq_sizes_t()
+    assert _wq.wq_sizes(h, C.byref(s)) == 0
+    w = Workload("t", p, nel, None, None)
+    assert s.nnz == w.exact_nnz()
+    assert tuple(s.n) == w.n_dof() + (1,)
+    assert tuple(s.n_qp) == tuple(2 * e + 2 * p - 1 for e in nel) + (1,)
+    assert s.n_rows == w.n_dof()[0] * w.n_dof()[1]
+    x = np.zeros(64)
+    assert _wq.wq_qpoints(h, 2, x.ctypes.data_as(C.POINTER(C.c_double))) == _wq.WQ_EINVAL
+    _wq.wq_plan_destroy(h)
+    good = open_uniform_knots(p, 8)
+    assert make([good], p, d=1)[0] == _wq.WQ_EINVAL
+    assert make([good] * 4, p, d=4)[0] == _wq.WQ_EINVAL
 
 
 @pytest.mark.parametrize("p,nel", [(2, (8, 8, 8)), (4, (32, 32, 32)), (6, (64, 64, 64)), (3, (5, 7, 9))])

@@ -1,0 +1,83 @@
+"""GPU parity of the 2D path (plane patches) against the oracle: the pattern
+bit-exact, FP64 values within 1e-12 row-normwise on every row (small cases)
+or on sampled rows, FP32 bulk within the rounding model of the 3D tests."""
+import numpy as np
+import pytest
+
+from parity_helpers import compare_rows, gather_rows, gpu_pipeline
+from workloads import coefficient_field, control_net, open_uniform_knots, random_open_knots
+
+pytestmark = pytest.mark.gpu
+
+FP64_TOL = 1e-12
+
+
+def _case(p, nel, seed, uniform):
+    kn = [open_uniform_knots(p, e) if uniform else random_open_knots(p, e, seed=seed + k)
+          for k, e in enumerate(nel)]
+    return kn, control_net(kn, p, seed=seed, amp_h=0.15)
+
+
+@pytest.mark.parametrize("p,nel,uniform,coef", [
+    (2, (6, 9), True, None), (3, (7, 5), False, 3), (4, (9, 8), False, None),
+    (5, (8, 11), True, 5), (6, (9, 10), False, 6)])
+def test_2d_all_rows(p, nel, uniform, coef):
+    import torch
+    from oracle.assembly import Problem
+    kn, ctrl = _case(p, nel, 20 + p, uniform)
+    cf = None if coef is None else coefficient_field(coef)
+    P = Problem(kn, p, ctrl, coef=cf)
+    print(f"[2d p={p} nel={nel} coef={coef}] running", flush=True)
+    plan, row_ptr, col_idx, mass, stiff = gpu_pipeline(kn, p, ctrl, cf, which=3)
+    rp_ref, ci_ref = P.csr_pattern()
+    assert np.array_equal(row_ptr.cpu().numpy(), rp_ref)
+    assert np.array_equal(col_idx.cpu().numpy(), ci_ref)
+    rows = np.arange(plan.n_rows)
+    for which, vals in (("mass", mass), ("stiff", stiff)):
+        rp, v = gather_rows(row_ptr, vals, rows)
+        row_err, mat_err, worst = compare_rows(P, rows, rp, v, which)
+        print(f"  {which}: row-normwise {row_err:.2e} (row {worst})", flush=True)
+        assert row_err <= FP64_TOL
+    lengths = row_ptr[1:] - row_ptr[:-1]
+    s1 = (torch.segment_reduce(stiff, "sum", lengths=lengths).abs()
+          / torch.segment_reduce(stiff.abs(), "sum", lengths=lengths)).max().item()
+    assert s1 <= 1e-13
+
+
+@pytest.mark.parametrize("p", [2, 4, 6])
+def test_2d_fp32_bulk(p):
+    from oracle.assembly import Problem
+    kn, ctrl = _case(p, (8, 9), 40 + p, False)
+    P = Problem(kn, p, ctrl)
+    plan, row_ptr, _, mass, stiff = gpu_pipeline(kn, p, ctrl, None, which=3, precision=1)
+    rows = np.arange(plan.n_rows)
+    tol = 16 * 2.0 ** -24 * np.sqrt((2 * p + 1) ** 2)
+    for which, vals in (("mass", mass), ("stiff", stiff)):
+        rp, v = gather_rows(row_ptr, vals, rows)
+        _, mat_err, _ = compare_rows(P, rows, rp, v, which)
+        print(f"[2d fp32 p={p}] {which}: matrix-normwise {mat_err:.2e} (bound {tol:.2e})", flush=True)
+        assert mat_err <= max(tol, 1e-5)
+
+
+def test_2d_large_sampled_rows():
+    """p = 4 on 128 x 96 elements: sampled rows (interior and boundary)."""
+    from oracle.assembly import Problem
+    p, nel = 4, (128, 96)
+    kn = [open_uniform_knots(p, e) for e in nel]
+    ctrl = control_net(kn, p, seed=77)
+    cf = coefficient_field(78)
+    P = Problem(kn, p, ctrl, coef=cf)
+    plan, row_ptr, col_idx, mass, stiff = gpu_pipeline(kn, p, ctrl, cf, which=3)
+    n1, n2 = P.n
+    rng = np.random.default_rng(5)
+    picks = [(0, 0), (1, 0), (n1 - 1, n2 - 1), (p, 3), (n1 - 2, 1), (2, n2 - 3)]
+    picks += [(int(a), int(b)) for a, b in zip(rng.integers(0, n1, 10), rng.integers(0, n2, 10))]
+    rows = np.array(sorted({i1 + n1 * i2 for i1, i2 in picks}))
+    rp, _ = gather_rows(row_ptr, stiff, rows)
+    for r in rows[:6]:
+        assert np.array_equal(col_idx[int(rp[r]):int(rp[r + 1])].cpu().numpy(), P.row_columns(int(r)))
+    for which, vals in (("mass", mass), ("stiff", stiff)):
+        rp, v = gather_rows(row_ptr, vals, rows)
+        row_err, _, worst = compare_rows(P, rows, rp, v, which)
+        print(f"[2d 128x96 p=4] {which}: row-normwise {row_err:.2e} (row {worst})", flush=True)
+        assert row_err <= FP64_TOL
