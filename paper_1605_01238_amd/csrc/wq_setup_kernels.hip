@@ -415,16 +415,34 @@ __global__ __launch_bounds__(256) void k_rules(PlanView v) {
     }
   }
   const double wq = live ? dd_to_double(w) : 0.0;
-  // residual of all ic equations (including a dropped one), in dd
-  double bmax = 0.0, rmax = 0.0;
+  // residual of all ic equations (including a dropped one); rows beyond
+  // #I_i are zero on both sides.  An FP64 sum with a bound on its rounding
+  // error settles the check when the bound allows (products and the a.lo
+  // terms: 2u each, the 6-level reduction: 6u, of the sum of magnitudes,
+  // doubled); otherwise it is decided in double-double.
+  double bmax = 0.0;
 #pragma unroll
-  for (int j = 0; j < IC; ++j) {   // rows beyond #I_i are zero on both sides
-    const dd a = live ? A[al][j][lane] : dd{0.0, 0.0};
-    const dd s = dd_wave_sum(a * wq);
-    bmax = fmax(bmax, fabs(bvec[pair][j].hi));
-    rmax = fmax(rmax, fabs(dd_to_double(s - bvec[pair][j])));
+  for (int j = 0; j < IC; ++j) bmax = fmax(bmax, fabs(bvec[pair][j].hi));
+  const double tol = 1e-9 * bmax + 1e-300;
+  bool certain = true;
+#pragma unroll
+  for (int j = 0; j < IC; ++j) {
+    const double ah = live ? A[al][j][lane].hi : 0.0;
+    const double s = wave_sum(ah * wq);
+    const double m = wave_sum(fabs(ah * wq));
+    const double err = 16.0 * 0x1p-53 * m + fabs(bvec[pair][j].lo);
+    if (!(fabs(s - bvec[pair][j].hi) + err <= tol)) certain = false;
   }
-  if (!(rmax <= 1e-9 * bmax + 1e-300) || broke) {
+  double rmax = 0.0;
+  if (!certain) {
+#pragma unroll
+    for (int j = 0; j < IC; ++j) {
+      const dd a = live ? A[al][j][lane] : dd{0.0, 0.0};
+      const dd s = dd_wave_sum(a * wq);
+      rmax = fmax(rmax, fabs(dd_to_double(s - bvec[pair][j])));
+    }
+  }
+  if (!(rmax <= tol) || broke) {
     if (lane == 0) {
       atomicAdd(&v.flags[FLAG_SOLVE_BAD], 1);
       atomicMin(&v.flags[FLAG_SOLVE_FIRST], (dir * 4 + pair) * n + i);
