@@ -59,9 +59,9 @@ enum : int { R00 = 0, R10 = 1, R01 = 2, R11 = 3 };
 // uses IC * J3 lanes); C: quadrature columns per chunk of phases A and B
 // (phase B has J3 * C * 4 items for the stiffness); WPE: waves per SIMD the
 // register allocation must allow (0: no bound).  Chosen by measurement.
-template <int P, typename T, bool STIFF> struct PushCfg;
+template <int P, typename T, bool STIFF, bool PLANE = false> struct PushCfg;
 #define WQ_PUSH_CFG(P_, T_, S_, NW_, J3_, C_, WPE_) \
-  template <> struct PushCfg<P_, T_, S_> { static constexpr int NW = NW_, J3 = J3_, C = C_, WPE = WPE_; };
+  template <> struct PushCfg<P_, T_, S_, false> { static constexpr int NW = NW_, J3 = J3_, C = C_, WPE = WPE_; };
 WQ_PUSH_CFG(2, double, false, 1, 5, 4, 0)
 WQ_PUSH_CFG(2, double, true, 1, 5, 3, 0)
 WQ_PUSH_CFG(3, double, false, 1, 7, 4, 0)
@@ -83,13 +83,19 @@ WQ_PUSH_CFG(5, float, true, 2, 11, 2, 0)
 WQ_PUSH_CFG(6, float, false, 3, 13, 8, 0)
 WQ_PUSH_CFG(6, float, true, 3, 13, 3, 0)
 #undef WQ_PUSH_CFG
-
+// Plane patches (d = 2: direction 3 is trivial, one j3 per pencil): one
+// wave with one j3 slot, and more quadrature columns per chunk for phase B.
 template <int P, typename T, bool STIFF>
+struct PushCfg<P, T, STIFF, true> {
+  static constexpr int NW = 1, J3 = 1, C = STIFF ? 4 : 8, WPE = 0;
+};
+
+template <int P, typename T, bool STIFF, bool PLANE = false>
 struct Shape {
-  using Cfg = PushCfg<P, T, STIFF>;
+  using Cfg = PushCfg<P, T, STIFF, PLANE>;
   static constexpr int IC = 2 * P + 1, QC = 3 * P + 1;
   static constexpr int NT = 64 * Cfg::NW, J3 = Cfg::J3, C = Cfg::C;
-  static constexpr int NPART = (IC + J3 - 1) / J3;        // j3 parts
+  static constexpr int NPART = PLANE ? 1 : (IC + J3 - 1) / J3;   // j3 parts (a plane patch has one j3)
   static constexpr int NG = STIFF ? 4 : 1;                // dir-1 rule groups
   static constexpr int NH = STIFF ? 6 : 1;                // merged dir-2 inputs
   static constexpr int NCH = STIFF ? 8 : 1;               // dir-3 channels
@@ -249,9 +255,9 @@ __global__ __launch_bounds__(256) void k_first(PlanView v) {
   }
 }
 
-template <int P, typename T, bool STIFF>
+template <int P, typename T, bool STIFF, bool PLANE>
 __device__ __forceinline__ void push_body(PlanView v, T* __restrict__ out, int nseg) {
-  using S = Shape<P, T, STIFF>;
+  using S = Shape<P, T, STIFF, PLANE>;
   constexpr int IC = S::IC, QC = S::QC, C = S::C, NT = S::NT, J3 = S::J3;
   constexpr int NG = S::NG, NH = S::NH, NCT = S::NCT;
   __shared__ __align__(16) T hbuf[S::HSBUF];    // [C][NH][QC][J3]   (c, h, qq2, u)
@@ -480,19 +486,19 @@ __device__ __forceinline__ void push_body(PlanView v, T* __restrict__ out, int n
 
 // The pencil kernel; configurations with WPE > 0 use the variant whose
 // register allocation is bounded for that many waves per SIMD.
-template <int P, typename T, bool STIFF>
-__global__ __launch_bounds__((Shape<P, T, STIFF>::NT)) void k_push(PlanView v, T* __restrict__ out, int nseg) {
-  push_body<P, T, STIFF>(v, out, nseg);
+template <int P, typename T, bool STIFF, bool PLANE>
+__global__ __launch_bounds__((Shape<P, T, STIFF, PLANE>::NT)) void k_push(PlanView v, T* __restrict__ out, int nseg) {
+  push_body<P, T, STIFF, PLANE>(v, out, nseg);
 }
 template <int P, typename T, bool STIFF>
 __global__ __launch_bounds__((Shape<P, T, STIFF>::NT))
 __attribute__((amdgpu_waves_per_eu(PushCfg<P, T, STIFF>::WPE))) void k_push_wpe(PlanView v, T* __restrict__ out, int nseg) {
-  push_body<P, T, STIFF>(v, out, nseg);
+  push_body<P, T, STIFF, false>(v, out, nseg);
 }
 
-template <int P, typename T, bool STIFF>
+template <int P, typename T, bool STIFF, bool PLANE>
 hipError_t push_launch(const PlanView& v, void* out, hipStream_t s) {
-  using Sh = Shape<P, T, STIFF>;
+  using Sh = Shape<P, T, STIFF, PLANE>;
   const int64_t wgs = int64_t(v.dir[1].n) * v.dir[2].n * Sh::NPART;
   // runs of at least 2p rows
   const int max_seg = std::max(1, v.dir[0].n / (2 * P));
@@ -501,21 +507,21 @@ hipError_t push_launch(const PlanView& v, void* out, hipStream_t s) {
   if (items <= 0 || items > INT32_MAX) return hipErrorInvalidConfiguration;
   const int64_t plane = int64_t(v.dir[0].nq) * v.dir[1].nq;
   hipLaunchKernelGGL((k_first<P, T, STIFF>), dim3(unsigned((plane + 255) / 256), unsigned(v.dir[2].n)), dim3(256), 0, s, v);
-  if constexpr (PushCfg<P, T, STIFF>::WPE > 0)
+  if constexpr (PushCfg<P, T, STIFF, PLANE>::WPE > 0)
     hipLaunchKernelGGL((k_push_wpe<P, T, STIFF>), dim3(unsigned(items)), dim3(Sh::NT), 0, s, v, static_cast<T*>(out), nseg);
   else
-    hipLaunchKernelGGL((k_push<P, T, STIFF>), dim3(unsigned(items)), dim3(Sh::NT), 0, s, v, static_cast<T*>(out), nseg);
+    hipLaunchKernelGGL((k_push<P, T, STIFF, PLANE>), dim3(unsigned(items)), dim3(Sh::NT), 0, s, v, static_cast<T*>(out), nseg);
   return hipGetLastError();
 }
 
 template <int P, typename T>
 hipError_t assemble_pt(const PlanView& v, int which, void* mass, void* stiff, hipStream_t s) {
   if (which & WQ_MASS) {
-    hipError_t e = push_launch<P, T, false>(v, mass, s);
+    hipError_t e = v.d == 2 ? push_launch<P, T, false, true>(v, mass, s) : push_launch<P, T, false, false>(v, mass, s);
     if (e != hipSuccess) return e;
   }
   if (which & WQ_STIFF) {
-    hipError_t e = push_launch<P, T, true>(v, stiff, s);
+    hipError_t e = v.d == 2 ? push_launch<P, T, true, true>(v, stiff, s) : push_launch<P, T, true, false>(v, stiff, s);
     if (e != hipSuccess) return e;
   }
   return hipSuccess;
