@@ -87,7 +87,7 @@ WQ_PUSH_CFG(6, float, true, 3, 13, 3, 0)
 // wave with one j3 slot, and more quadrature columns per chunk for phase B.
 template <int P, typename T, bool STIFF>
 struct PushCfg<P, T, STIFF, true> {
-  static constexpr int NW = 1, J3 = 1, C = STIFF ? 4 : 8, WPE = 0;
+  static constexpr int NW = 1, J3 = 1, C = STIFF ? 8 : 16, WPE = 0;
 };
 
 template <int P, typename T, bool STIFF, bool PLANE = false>
