@@ -117,7 +117,7 @@ def main():
     cf = w.coefficient()
     if cf is not None:
         plan.setup(ctrl)
-        x = plan.qp_physical().cpu().numpy().reshape(-1, 3)
+        x = plan.qp_physical().cpu().numpy().reshape(-1, plan.d)
         coef = torch.from_numpy(np.ascontiguousarray(cf(x))).cuda()
     row_ptr = torch.empty(plan.n_rows + 1, dtype=torch.int64, device="cuda")
     col_idx = torch.empty(plan.nnz, dtype=torch.int32, device="cuda")

@@ -81,3 +81,24 @@ def test_2d_large_sampled_rows():
         row_err, _, worst = compare_rows(P, rows, rp, v, which)
         print(f"[2d 128x96 p=4] {which}: row-normwise {row_err:.2e} (row {worst})", flush=True)
         assert row_err <= FP64_TOL
+
+
+def test_2d_setup_twice_then_again():
+    """setup(A) assemble, setup(B) assemble, setup(A) assemble on one plane
+    plan, no synchronization in between: each result equals a fresh plan's."""
+    import torch
+    from paper_1605_01238_amd import Plan
+    p, nel = 3, (7, 9)
+    kn = [random_open_knots(p, e, seed=60 + k) for k, e in enumerate(nel)]
+    nets = [control_net(kn, p, seed=s, amp_h=0.15) for s in (61, 62)]
+    refs = [gpu_pipeline(kn, p, c, None, which=3) for c in nets]
+    plan = Plan(kn, p)
+    plan.bind()
+    out = []
+    for c in (nets[0], nets[1], nets[0]):
+        plan.setup(torch.from_numpy(c).cuda())
+        out.append(plan.assemble(3))
+    plan.sync()
+    for (m, s), ref in zip(out, (refs[0], refs[1], refs[0])):
+        assert torch.equal(m, ref[3]) and torch.equal(s, ref[4])
+    assert not torch.equal(out[0][1], out[1][1])

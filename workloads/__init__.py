@@ -171,7 +171,11 @@ SWEEP = tuple(Workload(f"p{p}_{e}el_perturbed_coef", p, (e, e, e), geom_seed=10 
                        which=("stiff",))
               for p, e in ((4, 64), (5, 32), (5, 64), (6, 32)))
 
-WORKLOADS = {w.name: w for w in (SMALL_P2, MID_P4, LARGE_P6) + SWEEP}
+# plane patches (2D): perturbed Greville nets of the same recipe
+PLANE = (Workload("p4_512el_plane", 4, (512, 512), geom_seed=30, coef_seed=31, which=("stiff",)),
+         Workload("p6_256el_plane", 6, (256, 256), geom_seed=32, coef_seed=None, which=("stiff", "mass")))
+
+WORKLOADS = {w.name: w for w in (SMALL_P2, MID_P4, LARGE_P6) + SWEEP + PLANE}
 
 
 def sample_rows(n_dof3, p: int, n_uniform: int, n_boundary: int, seed: int) -> np.ndarray:
