@@ -185,10 +185,12 @@ __device__ inline void store_vec(T* __restrict__ p, const T (&v)[NV]) {
 // [jj3][c], is stored contiguously for the pencil kernel.  The 64 records of
 // a wavefront are one contiguous stretch of Y; they pass through LDS so that
 // consecutive lanes store consecutive elements (whole lines per store).
-template <int P, typename T, bool STIFF>
+// A plane patch (PLANE: direction 3 trivial) has only j3 = 0: one slot.
+template <int P, typename T, bool STIFF, bool PLANE = false>
 __global__ __launch_bounds__(256) void k_first(PlanView v) {
   constexpr int IC = 2 * P + 1, QC = 3 * P + 1, NCH = STIFF ? kYChannels : 1;
-  constexpr int REC = IC * NCH;                           // elements per record
+  constexpr int ICY = PLANE ? 1 : IC;                     // j3 slots per record
+  constexpr int REC = ICY * NCH;                          // elements per record
   constexpr int LPR = (9216 / int(sizeof(T) * REC)) < 64 ? (9216 / int(sizeof(T) * REC)) : 64;   // records per round
   __shared__ __align__(16) T stg[4][LPR * REC];
   const DirView d1 = v.dir[0], d2 = v.dir[1], d3 = v.dir[2];
@@ -208,9 +210,9 @@ __global__ __launch_bounds__(256) void k_first(PlanView v) {
   const T* __restrict__ T3 = op_t<T>(d3) + size_t(i3) * QC * IC * 4;    // [qq3][jj3][o]
   const int64_t N = v.nqtot;
   const T* __restrict__ f = static_cast<const T*>(v.field) + (valid ? l : l0) + plane * qs3;
-  T acc[IC * NCH];
+  T acc[ICY * NCH];
 #pragma unroll
-  for (int k = 0; k < IC * NCH; ++k) acc[k] = T(0);
+  for (int k = 0; k < ICY * NCH; ++k) acc[k] = T(0);
 #pragma unroll 2
   for (int qq3 = 0; qq3 < qc3; ++qq3) {
     const T* fk = f + plane * qq3;
@@ -219,7 +221,7 @@ __global__ __launch_bounds__(256) void k_first(PlanView v) {
       const T k11 = fk[1 * N], k22 = fk[2 * N], k33 = fk[3 * N];
       const T k12 = fk[4 * N], k13 = fk[5 * N], k23 = fk[6 * N];
 #pragma unroll
-      for (int jj = 0; jj < IC; ++jj) {
+      for (int jj = 0; jj < ICY; ++jj) {
         const T t0 = t[jj * 4 + R00], t1 = t[jj * 4 + R10], t2 = t[jj * 4 + R01], t3 = t[jj * 4 + R11];
         T* a = acc + jj * NCH;
         a[0] += t0 * k11;
@@ -234,7 +236,7 @@ __global__ __launch_bounds__(256) void k_first(PlanView v) {
     } else {
       const T k0 = fk[0];
 #pragma unroll
-      for (int jj = 0; jj < IC; ++jj) acc[jj] += t[jj * 4 + R00] * k0;
+      for (int jj = 0; jj < ICY; ++jj) acc[jj] += t[jj * 4 + R00] * k0;
     }
   }
   // the wave's records are contiguous in Y: pass them through LDS in rounds
@@ -295,7 +297,8 @@ __device__ __forceinline__ void push_body(PlanView v, T* __restrict__ out, int n
   const int qend = e1 == nel1 - 1 ? nq1 : P + 2 * e1 + 1;
 
   constexpr int NCH = S::NCH;
-  const T* __restrict__ Yb = static_cast<const T*>(v.ybuf) + int64_t(i3) * nq2 * nq1 * IC * NCH;   // [q2][q1][jj3][ch]
+  constexpr int ICY = PLANE ? 1 : IC;   // j3 slots per Y record (a plane patch has one)
+  const T* __restrict__ Yb = static_cast<const T*>(v.ybuf) + int64_t(i3) * nq2 * nq1 * ICY * NCH;   // [q2][q1][jj3][ch]
   const T* __restrict__ w2 = wt_t<T>(d2) + size_t(i2) * QC * 4;         // [qq2][o]
   const T* __restrict__ B2 = bt_t<T>(d2) + size_t(i2) * QC * IC * 2;    // [qq2][jj2][a]
   const T* __restrict__ CT = colt_t<T>(d1);                             // [q1][NCT]
@@ -361,7 +364,7 @@ __device__ __forceinline__ void push_body(PlanView v, T* __restrict__ out, int n
   for (int r = 0; r < RPL; ++r) {
     const int it = tid + r * NT;
     const int u = it % J3, c = (it / J3) % C, qq2 = it / (J3 * C);
-    roff[r] = (it < NREC && qq2 < qc2 && u < nj3) ? uint32_t(((qs2 + qq2) * nq1 + c) * IC + j3lo + u) * NCH : ~0u;
+    roff[r] = (it < NREC && qq2 < qc2 && u < nj3) ? uint32_t(((qs2 + qq2) * nq1 + c) * ICY + j3lo + u) * NCH : ~0u;
   }
   auto rec_valid = [&](int r, int col0) {
     const int c = ((tid + r * NT) / J3) % C;
@@ -370,7 +373,7 @@ __device__ __forceinline__ void push_body(PlanView v, T* __restrict__ out, int n
   auto fetch = [&](int col0) {
 #pragma unroll
     for (int r = 0; r < RPL; ++r) {
-      const uint32_t off = rec_valid(r, col0) ? roff[r] + uint32_t(col0 * IC * NCH) : 0u;
+      const uint32_t off = rec_valid(r, col0) ? roff[r] + uint32_t(col0 * ICY * NCH) : 0u;
       load_vec<T, NCH>(Yb + off, pre[r]);
     }
   };
@@ -506,7 +509,7 @@ hipError_t push_launch(const PlanView& v, void* out, hipStream_t s) {
   const int64_t items = wgs * nseg;
   if (items <= 0 || items > INT32_MAX) return hipErrorInvalidConfiguration;
   const int64_t plane = int64_t(v.dir[0].nq) * v.dir[1].nq;
-  hipLaunchKernelGGL((k_first<P, T, STIFF>), dim3(unsigned((plane + 255) / 256), unsigned(v.dir[2].n)), dim3(256), 0, s, v);
+  hipLaunchKernelGGL((k_first<P, T, STIFF, PLANE>), dim3(unsigned((plane + 255) / 256), unsigned(v.dir[2].n)), dim3(256), 0, s, v);
   if constexpr (PushCfg<P, T, STIFF, PLANE>::WPE > 0)
     hipLaunchKernelGGL((k_push_wpe<P, T, STIFF>), dim3(unsigned(items)), dim3(Sh::NT), 0, s, v, static_cast<T*>(out), nseg);
   else
