@@ -37,10 +37,15 @@
  * Memory and streams: the library never allocates device memory.  The
  * caller allocates one workspace (size from wq_sizes) and all outputs, and
  * owns them.  A bound plan owns one HIP stream and two events of its own
- * (see wq_setup), released by wq_plan_destroy.  Device calls are asynchronous on the given HIP stream
- * (0 = the legacy default stream).  Host pointers are read before the call
- * returns.  A plan is a host object; it is not thread-safe; distinct plans
- * are independent.
+ * (see wq_setup), released by wq_plan_destroy.  Device calls are
+ * asynchronous on the given HIP stream (0 = the legacy default stream).
+ * Host pointers are read before the call returns.  A plan is a host object;
+ * it is not thread-safe; distinct plans are independent.
+ * Ordering: the device calls of one plan share its workspace (tables, the
+ * coefficient field and the first-contraction buffer), so they must be
+ * ordered, e.g. issued on one stream; wq_assemble calls of one plan on
+ * different streams without such ordering race on that buffer.  Calls on
+ * distinct plans (distinct workspaces) may overlap freely.
  *
  * Errors: every call returns a wq_status; nothing is thrown across the ABI.
  * Host-detectable errors are returned immediately and leave the plan
@@ -152,8 +157,11 @@ wq_status wq_bind(wq_plan* plan, void* workspace, size_t bytes, hipStream_t stre
  */
 wq_status wq_setup(wq_plan* plan, const double* ctrl_dev, const double* coef_dev, hipStream_t stream);
 
-/* Recompute only the coefficient field for a new a (same geometry);
- * coef_dev as in wq_setup.  Requires a prior wq_setup. */
+/* New diffusion coefficient a on the same geometry: recomputes the
+ * coefficient field (the geometry stage of wq_setup; the univariate rules
+ * are kept); coef_dev as in wq_setup.  Requires a prior wq_setup.  Ordered
+ * like every other call of the plan (see Ordering above): an assembly
+ * still in flight on another stream must be waited for first. */
 wq_status wq_set_coefficient(wq_plan* plan, const double* coef_dev, hipStream_t stream);
 
 /* Physical quadrature points F(x_q) into x_dev[n_qp3][n_qp2][n_qp1][3]
@@ -205,7 +213,9 @@ wq_status wq_field(const wq_plan* plan, void* field_dev, hipStream_t stream);
  */
 wq_status wq_sync(wq_plan* plan, hipStream_t stream);
 
-/* Message for the last error of this plan (never NULL; "" if none). */
+/* Message for the last error of this plan (never NULL; "" if none).  With
+ * plan == NULL: the message of the last failed wq_plan_create on the calling
+ * thread (which knot vector failed which check). */
 const char* wq_last_error(const wq_plan* plan);
 
 /* Free the plan (host memory only; the caller frees its device buffers). */

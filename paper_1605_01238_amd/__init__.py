@@ -130,6 +130,8 @@ class Plan:
 
     def __del__(self):
         h = getattr(self, "_h", None)
-        if h is not None and h.value:
-            _wq.wq_plan_destroy(h)
+        # at interpreter exit the binding may already be torn down
+        destroy = getattr(_wq, "wq_plan_destroy", None) if _wq is not None else None
+        if h is not None and h.value and destroy is not None:
+            destroy(h)
             self._h = C.c_void_p()

@@ -71,6 +71,7 @@ class WQError(RuntimeError):
 
 
 def check(status: int, plan=None) -> None:
+    """Raise WQError for a failed call; the message is the plan's last error
+    (or, without a plan, that of the last failed wq_plan_create)."""
     if status != WQ_OK:
-        msg = lib.wq_last_error(plan).decode() if plan else ""
-        raise WQError(status, msg)
+        raise WQError(status, lib.wq_last_error(plan).decode())

@@ -133,5 +133,6 @@ hipError_t launch_prefix(const PlanView& v, hipStream_t s);
 hipError_t launch_ctrl_diff(const PlanView& v, const double* ctrl, hipStream_t s);
 hipError_t launch_geometry(const PlanView& v, const double* coef, double* xphys_out, hipStream_t s);
 hipError_t launch_pattern(const PlanView& v, int64_t* row_ptr, int32_t* col_idx, hipStream_t s);
+hipError_t launch_qranges(const PlanView& v, int dir, int32_t* q_start, int32_t* q_count, hipStream_t s);
 hipError_t launch_assemble(const PlanView& v, int which, void* mass, void* stiff, hipStream_t s);
 }  // namespace wq

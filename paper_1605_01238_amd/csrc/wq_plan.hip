@@ -12,6 +12,15 @@
 
 namespace {
 
+// Message of the last failed wq_plan_create of this thread (no plan exists
+// to carry it); returned by wq_last_error(NULL).
+thread_local std::string g_create_err;
+
+wq_status create_fail(wq_status st, const std::string& msg) {
+  g_create_err = msg;
+  return st;
+}
+
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 wq_status fail(wq_plan* plan, wq_status st, const std::string& msg) {
@@ -133,12 +142,14 @@ const char* wq_version(void) { return "wq-gfx950 0.1"; }
 
 wq_status wq_plan_create(int d, int p, const int64_t* n_knots, const double* const* knots,
                          int precision, wq_plan** out) {
-  if (!out) return WQ_EINVAL;
+  if (!out) return create_fail(WQ_EINVAL, "null output pointer");
   *out = nullptr;
-  if ((d != 2 && d != 3) || p < WQ_MIN_P || p > WQ_MAX_P || !n_knots || !knots) return WQ_EINVAL;
-  if (precision != WQ_FP64 && precision != WQ_FP32) return WQ_EINVAL;
+  if (d != 2 && d != 3) return create_fail(WQ_EINVAL, "d must be 2 or 3");
+  if (p < WQ_MIN_P || p > WQ_MAX_P) return create_fail(WQ_EINVAL, "degree outside the compiled range");
+  if (!n_knots || !knots) return create_fail(WQ_EINVAL, "null knot arrays");
+  if (precision != WQ_FP64 && precision != WQ_FP32) return create_fail(WQ_EINVAL, "precision must be WQ_FP64 or WQ_FP32");
   wq_plan* pl = new (std::nothrow) wq_plan();
-  if (!pl) return WQ_EINVAL;
+  if (!pl) return create_fail(WQ_EINVAL, "out of host memory");
   pl->d = d;
   pl->p = p;
   pl->prec = precision;
@@ -151,10 +162,16 @@ wq_status wq_plan_create(int d, int p, const int64_t* n_knots, const double* con
     pl->nq[k] = 1;
   }
   for (int k = 0; k < d; ++k) {
-    if (!knots[k] || n_knots[k] <= 0 || n_knots[k] > (int64_t(1) << 24)) { delete pl; return WQ_EINVAL; }
+    if (!knots[k] || n_knots[k] <= 0 || n_knots[k] > (int64_t(1) << 24)) {
+      delete pl;
+      return create_fail(WQ_EINVAL, "knot vector " + std::to_string(k) + ": null or bad length");
+    }
     int64_t nel = 0;
     std::string msg = check_knots(knots[k], n_knots[k], p, &nel);
-    if (!msg.empty()) { delete pl; return WQ_EKNOTS; }
+    if (!msg.empty()) {
+      delete pl;
+      return create_fail(WQ_EKNOTS, "knot vector " + std::to_string(k) + ": " + msg);
+    }
     pl->knots[k].assign(knots[k], knots[k] + n_knots[k]);
     pl->nel[k] = nel;
     pl->n[k] = nel + p;
@@ -163,12 +180,22 @@ wq_status wq_plan_create(int d, int p, const int64_t* n_knots, const double* con
     nnz *= (2 * p + 1) * pl->n[k] - p * (p + 1);   // Section 3, 1D count; tensor product
     nqtot *= pl->nq[k];
   }
-  // 32-bit index limits of the kernels: column and quadrature-point indices.
-  if (nrows >= (int64_t(1) << 31) || nqtot >= (int64_t(1) << 31)) { delete pl; return WQ_EINVAL; }
+  // 32-bit index limits of the kernels: column and quadrature-point indices,
+  // and element offsets within one i3 plane of the first-contraction buffer
+  if (nrows >= (int64_t(1) << 31) || nqtot >= (int64_t(1) << 31)) {
+    delete pl;
+    return create_fail(WQ_EINVAL, "patch too large: N_DOF and N_QP must stay below 2^31");
+  }
+  const int64_t yplane = pl->nq[0] * pl->nq[1] * (d == 3 ? wq::icap_of(p) : 1) * wq::kYChannels;
+  if (yplane >= (int64_t(1) << 32)) {
+    delete pl;
+    return create_fail(WQ_EINVAL, "patch too large: n_qp1 * n_qp2 * (2p+1) * 8 must stay below 2^32");
+  }
   pl->nrows = nrows;
   pl->nnz = nnz;
   pl->nqtot = nqtot;
   compute_layout(pl);
+  g_create_err.clear();
   *out = pl;
   return WQ_OK;
 }
@@ -333,16 +360,8 @@ wq_status wq_weights(const wq_plan* plan, int dir, int pair, double* w_dev, int3
                      hipMemcpyDeviceToDevice, stream);
   if (e != hipSuccess) return WQ_EDEVICE;
   if (qs_dev || qc_dev) {
-    std::vector<int32_t> s(n), c(n);
-    for (int i = 0; i < n; ++i) {
-      int a, b;
-      wq::q_range(i, p, int(plan->nel[dir]), a, b);
-      s[i] = a;
-      c[i] = b;
-    }
-    // synchronous copies from pageable memory: the vectors die with this call
-    if (qs_dev && hipMemcpy(qs_dev, s.data(), n * 4, hipMemcpyHostToDevice) != hipSuccess) return WQ_EDEVICE;
-    if (qc_dev && hipMemcpy(qc_dev, c.data(), n * 4, hipMemcpyHostToDevice) != hipSuccess) return WQ_EDEVICE;
+    e = wq::launch_qranges(plan->view(), dir, qs_dev, qc_dev, stream);
+    if (e != hipSuccess) return WQ_EDEVICE;
   }
   return WQ_OK;
 }
@@ -384,7 +403,7 @@ wq_status wq_sync(wq_plan* plan, hipStream_t stream) {
   return st;
 }
 
-const char* wq_last_error(const wq_plan* plan) { return plan ? plan->err.c_str() : "null plan"; }
+const char* wq_last_error(const wq_plan* plan) { return plan ? plan->err.c_str() : g_create_err.c_str(); }
 
 void wq_plan_destroy(wq_plan* plan) { delete plan; }
 

@@ -488,6 +488,18 @@ __global__ void k_prefix(PlanView v) {
   }
 }
 
+// Q_i = [q_start[i], q_start[i] + q_count[i]) of one direction (either
+// output may be null).
+__global__ void k_qranges(PlanView v, int dir, int32_t* __restrict__ q_start, int32_t* __restrict__ q_count) {
+  const DirView d = v.dir[dir];
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= d.n) return;
+  int qs, qc;
+  q_range(i, v.p, d.nel, qs, qc);
+  if (q_start) q_start[i] = qs;
+  if (q_count) q_count[i] = qc;
+}
+
 // ---------------------------------------------------------------------------
 // Physical coordinates F = sum_i C_i B_i at every quadrature point (used to
 // sample a coefficient given as a function of x).
@@ -875,6 +887,12 @@ hipError_t launch_geometry(const PlanView& v, const double* coef, double* xphys,
 #define C(P) geometry_p<P>(v, coef, xphys, s)
   WQ_DISPATCH_P(v.p, C)
 #undef C
+}
+
+hipError_t launch_qranges(const PlanView& v, int dir, int32_t* q_start, int32_t* q_count, hipStream_t s) {
+  const int n = v.dir[dir].n;
+  hipLaunchKernelGGL(k_qranges, dim3(unsigned((n + 255) / 256)), dim3(256), 0, s, v, dir, q_start, q_count);
+  return hipGetLastError();
 }
 
 hipError_t launch_prefix(const PlanView& v, hipStream_t s) {

@@ -114,6 +114,12 @@ def test_invalid_inputs_rejected():
     assert make([good, few, good], 3)[0] == _wq.WQ_EKNOTS
     nan = good.copy(); nan[4] = np.nan
     assert make([good, good, nan], 3)[0] == _wq.WQ_EKNOTS
+    # the failed creation's message names the knot vector and the check
+    assert make([good, good, rep], 3)[0] == _wq.WQ_EKNOTS
+    msg = _wq.wq_last_error(None).decode()
+    assert "knot vector 2" in msg and "simple" in msg, msg
+    assert make([good, few, good], 3)[0] == _wq.WQ_EKNOTS
+    assert "knot vector 1" in _wq.wq_last_error(None).decode()
     h = C.c_void_p()
     assert _wq.wq_plan_create(3, 3, None, None, 0, C.byref(h)) == _wq.WQ_EINVAL
 
@@ -134,4 +140,23 @@ def test_state_and_workspace_errors_without_device():
     assert _wq.wq_bind(h, dummy, 16, None) == _wq.WQ_ENOSPACE
     assert _wq.wq_bind(h, C.c_void_p(257), 1 << 40, None) == _wq.WQ_ENOSPACE
     assert b"256-byte" in _wq.wq_last_error(h)
+    _wq.wq_plan_destroy(h)
+
+
+def test_first_contraction_offset_limit():
+    """Offsets within one i3 plane of the first-contraction buffer are 32-bit
+    in the kernels: a patch whose plane holds 2^32 elements or more is
+    refused at creation (thin in direction 3, so N_QP itself stays legal)."""
+    from paper_1605_01238_amd import _wq
+    from workloads import open_uniform_knots
+    p = 2
+    # n_qp = 2 n_el + 2p - 1; plane elements n_qp1 n_qp2 (2p+1) 8
+    big = open_uniform_knots(p, 5200)    # n_qp = 10403: 10403^2 * 40 > 2^32, N_QP = 10403^2 * 11 < 2^31
+    thin = open_uniform_knots(p, p + 2)
+    st, _ = make([big, big, thin], p)
+    assert st == _wq.WQ_EINVAL
+    assert "2^32" in _wq.wq_last_error(None).decode()
+    ok = open_uniform_knots(p, 2000)     # 4003^2 * 40 < 2^32
+    st, h = make([ok, ok, thin], p)
+    assert st == 0
     _wq.wq_plan_destroy(h)
