@@ -85,39 +85,6 @@ struct DirView {
   float* colt32;
 };
 
-// Per-span operand tables of the direction-1 contraction in the lane layout
-// of the 16x16x4 matrix instructions (see the pencil kernel).  For knot-span
-// e of direction 1 and k-step ks, lane l = m + 16k of the A table holds
-// B^(alpha)_{e+m-p}(x_q) (0 unless 0 <= m-p <= p): the operand of the open
-// row e (s = 0); row e+s uses the same values moved up by s lanes.  The point
-// is q = first point of e + c with (c, alpha) = (kappa/2, kappa%2),
-// kappa = 4 ks + k (the mass uses alpha = 0 only: its alpha = 1 entries
-// are zero).  The weight
-// tables hold, per (e, ks, s, k), the weights of row e+s at that point:
-// (w^(alpha,0), w^(alpha,1)) for the stiffness, w^(0,0) for the mass.
-struct LaneTables {
-  int kss, ksm;           // k-steps per span (stiffness, mass)
-  size_t a64, w64, am64, wm64, a32, w32, am32, wm32, total;   // byte offsets
-};
-__host__ __device__ inline LaneTables lane_tables(int p, int nel1) {
-  LaneTables t;
-  t.kss = (2 * (p + 2) + 3) / 4;
-  t.ksm = t.kss;
-  const size_t ne = size_t(nel1), nw = size_t(nel1) * (p + 1);
-  size_t off = 0;
-  auto take = [&](size_t bytes) { size_t o = off; off += (bytes + 255) & ~size_t(255); return o; };
-  t.a64 = take(ne * t.kss * 64 * 8);
-  t.w64 = take(nw * t.kss * 4 * 2 * 8);
-  t.am64 = take(ne * t.ksm * 64 * 8);
-  t.wm64 = take(nw * t.ksm * 4 * 8);
-  t.a32 = take(ne * t.kss * 64 * 4);
-  t.w32 = take(nw * t.kss * 4 * 2 * 4);
-  t.am32 = take(ne * t.ksm * 64 * 4);
-  t.wm32 = take(nw * t.ksm * 4 * 4);
-  t.total = off;
-  return t;
-}
-
 struct PlanView {
   int p;
   int prec;
@@ -126,7 +93,6 @@ struct PlanView {
   DirView dir[3];
   void* field;           // kNumChannels * nqtot in the plan precision
   void* ybuf;            // [n3][nq2][nq1][icap][kYChannels]: field contracted over q3 per test index i3
-  char* lanes;           // per-span operand tables of direction 1 (LaneTables)
   double* ctrl;          // n3*n2*n1*3 (n2*n1*2 in 2D)
   double* dctrl;         // 3 * n3*n2*n1*3: C_i - C_{i - e_b} along direction b (0 where i_b = 0)
   int32_t* flags;        // kNumFlags
@@ -135,7 +101,7 @@ struct PlanView {
 
 struct Layout {
   size_t knots[3], x[3], qspan[3], bv[3], bd[3], bw[3], w[3], op64[3], op32[3], bt64[3], bt32[3], wt64[3], wt32[3], prefix[3], colt64[3], colt32[3];
-  size_t field, ybuf, lanes, ctrl, dctrl, flags, total;
+  size_t field, ybuf, ctrl, dctrl, flags, total;
 };
 
 }  // namespace wq
@@ -163,7 +129,6 @@ namespace wq {
 // Kernel launchers (return hipError_t of the launch).
 hipError_t launch_points(const PlanView& v, hipStream_t s);
 hipError_t launch_rules(const PlanView& v, hipStream_t s);
-hipError_t launch_lanes(const PlanView& v, hipStream_t s);
 hipError_t launch_prefix(const PlanView& v, hipStream_t s);
 hipError_t launch_ctrl_diff(const PlanView& v, const double* ctrl, hipStream_t s);
 hipError_t launch_geometry(const PlanView& v, const double* coef, double* xphys_out, hipStream_t s);

@@ -83,7 +83,6 @@ void compute_layout(wq_plan* pl) {
   const size_t ybytes = size_t(pl->n[2]) * size_t(pl->nq[1]) * size_t(pl->nq[0]) * ic * wq::kYChannels * elem;
   const size_t gbytes = size_t(pl->nq[2]) * size_t(pl->n[0]) * (size_t(pl->n[1]) + size_t(pl->nq[1])) * 9 * 8;
   L.ybuf = take(ybytes > gbytes ? ybytes : gbytes);
-  L.lanes = take(wq::lane_tables(p, int(pl->nel[0])).total);
   L.ctrl = take(size_t(pl->nrows) * 3 * 8);
   L.dctrl = take(size_t(pl->nrows) * 9 * 8);
   L.flags = take(wq::kNumFlags * 4);
@@ -130,7 +129,6 @@ wq::PlanView wq_plan::view() const {
   }
   v.field = ws + lay.field;
   v.ybuf = ws + lay.ybuf;
-  v.lanes = ws + lay.lanes;
   v.ctrl = reinterpret_cast<double*>(ws + lay.ctrl);
   v.dctrl = reinterpret_cast<double*>(ws + lay.dctrl);
   v.flags = reinterpret_cast<int32_t*>(ws + lay.flags);
@@ -300,7 +298,6 @@ wq_status wq_setup(wq_plan* plan, const double* ctrl_dev, const double* coef_dev
   e = hipEventRecord(plan->ev_fork, stream);
   if (e == hipSuccess) e = hipStreamWaitEvent(plan->aux, plan->ev_fork, 0);
   if (e == hipSuccess) e = wq::launch_rules(v, plan->aux);
-  if (e == hipSuccess) e = wq::launch_lanes(v, plan->aux);
   if (e == hipSuccess) e = hipEventRecord(plan->ev_rules, plan->aux);
   if (e != hipSuccess) return hip_fail(plan, e, "wq_setup: univariate kernel");
   plan->rules_launched = true;
