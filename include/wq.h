@@ -192,6 +192,25 @@ wq_status wq_assemble(wq_plan* plan, int which, void* mass_vals_dev, void* stiff
                       hipStream_t stream);
 
 /*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): the same
+ * values as wq_assemble (same arguments, same results bit for bit) with the
+ * first-contraction buffer taken from a static scratch array of the library
+ * instead of the workspace.  The array is WQ_STATIC_SCRATCH_BYTES per GPU,
+ * held from the loading of the library until the process ends; the patch is
+ * formed in slabs of i3 planes that fit in it.  The call allocates nothing
+ * (no hipMalloc, no allocating library routine).  Every call on one GPU
+ * shares that GPU's array: calls that overlap on one GPU (different streams,
+ * different plans) race and must be ordered by the caller.
+ * Errors: as wq_assemble; WQ_ENOSPACE if one plane of the buffer,
+ * n_qp1 * n_qp2 * (2p+1, or 1 for d = 2) * (8 channels with WQ_STIFF, else
+ * 1) * value size, exceeds the array.
+ */
+#define WQ_STATIC_SCRATCH_BYTES ((size_t)64 << 20)
+wq_status wq_assemble_static(wq_plan* plan, int which, void* mass_vals_dev, void* stiff_vals_dev,
+                             hipStream_t stream);
+
+/*
  * Export intermediate products for inspection/testing (device, asynchronous):
  *   wq_weights: the FP64 weights of direction dir and pairing index
  *     pair = 2*beta + alpha for (alpha, beta) in {(0,0),(1,0),(0,1),(1,1)},

@@ -12,9 +12,9 @@ from typing import Optional, Sequence
 import numpy as np
 
 from . import _wq
-from ._wq import (WQ_FP32, WQ_FP64, WQ_MASS, WQ_STIFF, WQError, check)
+from ._wq import (WQ_FP32, WQ_FP64, WQ_MASS, WQ_STATIC_SCRATCH_BYTES, WQ_STIFF, WQError, check)
 
-__all__ = ["Plan", "WQError", "WQ_FP32", "WQ_FP64", "WQ_MASS", "WQ_STIFF"]
+__all__ = ["Plan", "WQError", "WQ_FP32", "WQ_FP64", "WQ_MASS", "WQ_STATIC_SCRATCH_BYTES", "WQ_STIFF"]
 
 
 def _ptr(t) -> Optional[int]:

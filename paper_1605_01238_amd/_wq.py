@@ -16,6 +16,7 @@ WQ_OK, WQ_EINVAL, WQ_EKNOTS, WQ_ESINGULAR, WQ_EGEOM, WQ_ENOSPACE, WQ_EDEVICE, WQ
 WQ_MASS, WQ_STIFF = 1, 2
 WQ_FP64, WQ_FP32 = 0, 1
 WQ_MIN_P, WQ_MAX_P = 2, 6
+WQ_STATIC_SCRATCH_BYTES = 64 << 20   # static scratch of wq_assemble_static, per GPU
 
 STATUS_NAMES = {0: "WQ_OK", -1: "WQ_EINVAL", -2: "WQ_EKNOTS", -3: "WQ_ESINGULAR", -4: "WQ_EGEOM",
                 -5: "WQ_ENOSPACE", -6: "WQ_EDEVICE", -7: "WQ_ESTATE"}
@@ -40,6 +41,7 @@ SIGNATURES = [
     ("wq_qp_physical", C.c_int, [_P, _P, _P]),
     ("wq_pattern", C.c_int, [_P, _P, _P, _P]),
     ("wq_assemble", C.c_int, [_P, C.c_int, _P, _P, _P]),
+    ("wq_assemble_static", C.c_int, [_P, C.c_int, _P, _P, _P]),
     ("wq_weights", C.c_int, [_P, C.c_int, C.c_int, _P, _P, _P, _P]),
     ("wq_field", C.c_int, [_P, _P, _P]),
     ("wq_sync", C.c_int, [_P, _P]),

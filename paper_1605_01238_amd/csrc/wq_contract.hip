@@ -40,6 +40,7 @@
 
 #include <algorithm>
 #include <climits>
+#include <mutex>
 
 #include "wq_internal.h"
 
@@ -198,7 +199,7 @@ __global__ __launch_bounds__(256) void k_first(PlanView v) {
   const int tid = threadIdx.x, wv = tid / 64, ln = tid % 64;
   const int64_t l0 = int64_t(blockIdx.x) * blockDim.x + wv * 64;   // first point of the wave
   const int64_t l = l0 + ln;
-  const int i3 = blockIdx.y;
+  const int i3 = v.y_i3 + blockIdx.y;   // Y holds the planes i3 >= y_i3
   if (l0 >= plane) return;   // uniform per wave
   const bool valid = l < plane;
   int qs3, qc3;
@@ -242,7 +243,7 @@ __global__ __launch_bounds__(256) void k_first(PlanView v) {
   // the wave's records are contiguous in Y: pass them through LDS in rounds
   // of LPR records so that consecutive lanes store consecutive elements
   const int nvalid = int(plane - l0 < 64 ? plane - l0 : 64);
-  T* y = static_cast<T*>(v.ybuf) + (int64_t(i3) * plane + l0) * REC;
+  T* y = static_cast<T*>(v.ybuf) + (int64_t(i3 - v.y_i3) * plane + l0) * REC;
   T* st = stg[wv];
   for (int r0 = 0; r0 < nvalid; r0 += LPR) {
     if (ln >= r0 && ln < r0 + LPR) store_vec<T, REC>(st + (ln - r0) * REC, acc);
@@ -258,7 +259,7 @@ __global__ __launch_bounds__(256) void k_first(PlanView v) {
 }
 
 template <int P, typename T, bool STIFF, bool PLANE>
-__device__ __forceinline__ void push_body(PlanView v, T* __restrict__ out, int nseg) {
+__device__ __forceinline__ void push_body(PlanView v, T* __restrict__ out, int nseg, int item0) {
   using S = Shape<P, T, STIFF, PLANE>;
   constexpr int IC = S::IC, QC = S::QC, C = S::C, NT = S::NT, J3 = S::J3;
   constexpr int NG = S::NG, NH = S::NH, NCT = S::NCT;
@@ -275,7 +276,7 @@ __device__ __forceinline__ void push_body(PlanView v, T* __restrict__ out, int n
   // which read overlapping coefficient blocks, share an L2.
   const int total = gridDim.x, L = blockIdx.x;
   const int xcd = L % 8, kx = L / 8, m8 = total / 8, r8 = total % 8;
-  int item = xcd * m8 + min(xcd, r8) + kx;
+  int item = item0 + xcd * m8 + min(xcd, r8) + kx;
   const int part = item % S::NPART;
   item /= S::NPART;
   const int i2 = item % n2;
@@ -298,7 +299,7 @@ __device__ __forceinline__ void push_body(PlanView v, T* __restrict__ out, int n
 
   constexpr int NCH = S::NCH;
   constexpr int ICY = PLANE ? 1 : IC;   // j3 slots per Y record (a plane patch has one)
-  const T* __restrict__ Yb = static_cast<const T*>(v.ybuf) + int64_t(i3) * nq2 * nq1 * ICY * NCH;   // [q2][q1][jj3][ch]
+  const T* __restrict__ Yb = static_cast<const T*>(v.ybuf) + int64_t(i3 - v.y_i3) * nq2 * nq1 * ICY * NCH;   // [q2][q1][jj3][ch]
   const T* __restrict__ w2 = wt_t<T>(d2) + size_t(i2) * QC * 4;         // [qq2][o]
   const T* __restrict__ B2 = bt_t<T>(d2) + size_t(i2) * QC * IC * 2;    // [qq2][jj2][a]
   const T* __restrict__ CT = colt_t<T>(d1);                             // [q1][NCT]
@@ -490,17 +491,20 @@ __device__ __forceinline__ void push_body(PlanView v, T* __restrict__ out, int n
 // The pencil kernel; configurations with WPE > 0 use the variant whose
 // register allocation is bounded for that many waves per SIMD.
 template <int P, typename T, bool STIFF, bool PLANE>
-__global__ __launch_bounds__((Shape<P, T, STIFF, PLANE>::NT)) void k_push(PlanView v, T* __restrict__ out, int nseg) {
-  push_body<P, T, STIFF, PLANE>(v, out, nseg);
+__global__ __launch_bounds__((Shape<P, T, STIFF, PLANE>::NT)) void k_push(PlanView v, T* __restrict__ out, int nseg, int item0) {
+  push_body<P, T, STIFF, PLANE>(v, out, nseg, item0);
 }
 template <int P, typename T, bool STIFF>
 __global__ __launch_bounds__((Shape<P, T, STIFF>::NT))
-__attribute__((amdgpu_waves_per_eu(PushCfg<P, T, STIFF>::WPE))) void k_push_wpe(PlanView v, T* __restrict__ out, int nseg) {
-  push_body<P, T, STIFF, false>(v, out, nseg);
+__attribute__((amdgpu_waves_per_eu(PushCfg<P, T, STIFF>::WPE))) void k_push_wpe(PlanView v, T* __restrict__ out, int nseg, int item0) {
+  push_body<P, T, STIFF, false>(v, out, nseg, item0);
 }
 
+// The rows of the pencils with i3 in [i3a, i3b): k_first fills the Y planes
+// of that slab (v.ybuf holds the planes from v.y_i3 on), k_push forms them.
+// Workgroups are ordered i3 slowest, so a slab is a contiguous item range.
 template <int P, typename T, bool STIFF, bool PLANE>
-hipError_t push_launch(const PlanView& v, void* out, hipStream_t s) {
+hipError_t push_launch(const PlanView& v, void* out, hipStream_t s, int i3a, int i3b) {
   using Sh = Shape<P, T, STIFF, PLANE>;
   const int64_t wgs = int64_t(v.dir[1].n) * v.dir[2].n * Sh::NPART;
   // runs of at least 2p rows
@@ -508,45 +512,107 @@ hipError_t push_launch(const PlanView& v, void* out, hipStream_t s) {
   const int nseg = int(std::min<int64_t>(max_seg, std::max<int64_t>(1, (WQ_WG_TARGET + wgs - 1) / wgs)));
   const int64_t items = wgs * nseg;
   if (items <= 0 || items > INT32_MAX) return hipErrorInvalidConfiguration;
+  const int64_t per_i3 = items / v.dir[2].n;
   const int64_t plane = int64_t(v.dir[0].nq) * v.dir[1].nq;
-  hipLaunchKernelGGL((k_first<P, T, STIFF, PLANE>), dim3(unsigned((plane + 255) / 256), unsigned(v.dir[2].n)), dim3(256), 0, s, v);
+  if (i3b <= i3a) return hipSuccess;
+  hipLaunchKernelGGL((k_first<P, T, STIFF, PLANE>), dim3(unsigned((plane + 255) / 256), unsigned(i3b - i3a)), dim3(256), 0, s, v);
+  const dim3 grid(unsigned(per_i3 * (i3b - i3a)));
+  const int item0 = int(per_i3 * i3a);
   if constexpr (PushCfg<P, T, STIFF, PLANE>::WPE > 0)
-    hipLaunchKernelGGL((k_push_wpe<P, T, STIFF>), dim3(unsigned(items)), dim3(Sh::NT), 0, s, v, static_cast<T*>(out), nseg);
+    hipLaunchKernelGGL((k_push_wpe<P, T, STIFF>), grid, dim3(Sh::NT), 0, s, v, static_cast<T*>(out), nseg, item0);
   else
-    hipLaunchKernelGGL((k_push<P, T, STIFF, PLANE>), dim3(unsigned(items)), dim3(Sh::NT), 0, s, v, static_cast<T*>(out), nseg);
+    hipLaunchKernelGGL((k_push<P, T, STIFF, PLANE>), grid, dim3(Sh::NT), 0, s, v, static_cast<T*>(out), nseg, item0);
   return hipGetLastError();
 }
 
 template <int P, typename T>
-hipError_t assemble_pt(const PlanView& v, int which, void* mass, void* stiff, hipStream_t s) {
+hipError_t assemble_pt(const PlanView& v, int which, void* mass, void* stiff, hipStream_t s, int i3a, int i3b) {
   if (which & WQ_MASS) {
-    hipError_t e = v.d == 2 ? push_launch<P, T, false, true>(v, mass, s) : push_launch<P, T, false, false>(v, mass, s);
+    hipError_t e = v.d == 2 ? push_launch<P, T, false, true>(v, mass, s, i3a, i3b)
+                            : push_launch<P, T, false, false>(v, mass, s, i3a, i3b);
     if (e != hipSuccess) return e;
   }
   if (which & WQ_STIFF) {
-    hipError_t e = v.d == 2 ? push_launch<P, T, true, true>(v, stiff, s) : push_launch<P, T, true, false>(v, stiff, s);
+    hipError_t e = v.d == 2 ? push_launch<P, T, true, true>(v, stiff, s, i3a, i3b)
+                            : push_launch<P, T, true, false>(v, stiff, s, i3a, i3b);
     if (e != hipSuccess) return e;
   }
   return hipSuccess;
 }
 
 template <int P>
-hipError_t assemble_p(const PlanView& v, int which, void* mass, void* stiff, hipStream_t s) {
-  return v.prec == WQ_FP64 ? assemble_pt<P, double>(v, which, mass, stiff, s)
-                           : assemble_pt<P, float>(v, which, mass, stiff, s);
+hipError_t assemble_p(const PlanView& v, int which, void* mass, void* stiff, hipStream_t s, int i3a, int i3b) {
+  return v.prec == WQ_FP64 ? assemble_pt<P, double>(v, which, mass, stiff, s, i3a, i3b)
+                           : assemble_pt<P, float>(v, which, mass, stiff, s, i3a, i3b);
+}
+
+hipError_t assemble_slab(const PlanView& v, int which, void* mass, void* stiff, hipStream_t s, int i3a, int i3b) {
+  switch (v.p) {
+    case 2: return assemble_p<2>(v, which, mass, stiff, s, i3a, i3b);
+    case 3: return assemble_p<3>(v, which, mass, stiff, s, i3a, i3b);
+    case 4: return assemble_p<4>(v, which, mass, stiff, s, i3a, i3b);
+    case 5: return assemble_p<5>(v, which, mass, stiff, s, i3a, i3b);
+    case 6: return assemble_p<6>(v, which, mass, stiff, s, i3a, i3b);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+// Scratch of the allocation-free assembly: the first-contraction buffer Y
+// for a slab of i3 planes.  Each GPU the library runs on holds its own copy
+// (loaded with the code object, kept until the process ends); its address
+// on a device comes from hipGetSymbolAddress, taken once per device.
+static __device__ __align__(256) char scratch[kStaticScratchBytes];
+
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+hipError_t scratch_on_current_device(void** out) {
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return hipSuccess;
 }
 
 }  // namespace
 
 hipError_t launch_assemble(const PlanView& v, int which, void* mass, void* stiff, hipStream_t s) {
-  switch (v.p) {
-    case 2: return assemble_p<2>(v, which, mass, stiff, s);
-    case 3: return assemble_p<3>(v, which, mass, stiff, s);
-    case 4: return assemble_p<4>(v, which, mass, stiff, s);
-    case 5: return assemble_p<5>(v, which, mass, stiff, s);
-    case 6: return assemble_p<6>(v, which, mass, stiff, s);
-    default: return hipErrorInvalidValue;
+  PlanView w = v;
+  w.y_i3 = 0;
+  return assemble_slab(w, which, mass, stiff, s, 0, v.dir[2].n);
+}
+
+size_t static_plane_bytes(const PlanView& v, int which) {
+  const size_t elem = v.prec == WQ_FP64 ? 8 : 4;
+  const size_t icy = v.d == 2 ? 1 : size_t(icap_of(v.p));
+  const size_t nch = (which & WQ_STIFF) ? size_t(kYChannels) : 1;
+  return size_t(v.dir[0].nq) * size_t(v.dir[1].nq) * icy * nch * elem;
+}
+
+hipError_t launch_assemble_static(const PlanView& v, int which, void* mass, void* stiff, hipStream_t s) {
+  const size_t pb = static_plane_bytes(v, which);
+  const int per_slab = int(std::min<size_t>(kStaticScratchBytes / pb, size_t(v.dir[2].n)));
+  if (per_slab < 1) return hipErrorInvalidValue;   // refused by the caller beforehand
+  void* ptr = nullptr;
+  hipError_t e = scratch_on_current_device(&ptr);
+  if (e != hipSuccess) return e;
+  PlanView w = v;
+  w.ybuf = ptr;
+  for (int a = 0; a < v.dir[2].n; a += per_slab) {
+    const int b = std::min(v.dir[2].n, a + per_slab);
+    w.y_i3 = a;
+    e = assemble_slab(w, which, mass, stiff, s, a, b);
+    if (e != hipSuccess) return e;
   }
+  return hipSuccess;
 }
 
 }  // namespace wq

@@ -26,6 +26,9 @@ namespace wq {
 constexpr int kNumChannels = 7;   // det J, K11, K22, K33, K12, K13, K23
 constexpr int kYChannels = 8;     // distinct (coefficient, dir-3 rule) pairs of the stiffness
 constexpr int kNumFlags = 16;
+// Scratch of the allocation-free assembly (a static device array per GPU).
+constexpr size_t kStaticScratchBytes = WQ_STATIC_SCRATCH_BYTES;
+constexpr int kMaxDevices = 64;
 
 // Latched device conditions (int32 counters in the workspace).
 enum Flag : int {
@@ -97,6 +100,7 @@ struct PlanView {
   double* dctrl;         // 3 * n3*n2*n1*3: C_i - C_{i - e_b} along direction b (0 where i_b = 0)
   int32_t* flags;        // kNumFlags
   int64_t nqtot;
+  int y_i3;              // ybuf holds the first-contraction planes i3 >= y_i3
 };
 
 struct Layout {
@@ -135,4 +139,9 @@ hipError_t launch_geometry(const PlanView& v, const double* coef, double* xphys_
 hipError_t launch_pattern(const PlanView& v, int64_t* row_ptr, int32_t* col_idx, hipStream_t s);
 hipError_t launch_qranges(const PlanView& v, int dir, int32_t* q_start, int32_t* q_count, hipStream_t s);
 hipError_t launch_assemble(const PlanView& v, int which, void* mass, void* stiff, hipStream_t s);
+// The same rows with the first-contraction buffer in the library's static
+// scratch, i3 plane slab by slab (no allocation of any kind).
+hipError_t launch_assemble_static(const PlanView& v, int which, void* mass, void* stiff, hipStream_t s);
+// Bytes of one first-contraction plane (one i3) for the matrices of `which`.
+size_t static_plane_bytes(const PlanView& v, int which);
 }  // namespace wq

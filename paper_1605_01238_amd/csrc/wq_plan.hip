@@ -348,6 +348,27 @@ wq_status wq_assemble(wq_plan* plan, int which, void* mass, void* stiff, hipStre
   return WQ_OK;
 }
 
+wq_status wq_assemble_static(wq_plan* plan, int which, void* mass, void* stiff, hipStream_t stream) {
+  if (!plan) return WQ_EINVAL;
+  if (which <= 0 || (which & ~(WQ_MASS | WQ_STIFF))) return fail(plan, WQ_EINVAL, "which must be WQ_MASS, WQ_STIFF or both");
+  if ((which & WQ_MASS) && !mass) return fail(plan, WQ_EINVAL, "null mass output");
+  if ((which & WQ_STIFF) && !stiff) return fail(plan, WQ_EINVAL, "null stiffness output");
+  if (!plan->setup_done) return fail(plan, WQ_ESTATE, "wq_assemble_static before wq_setup");
+  const wq::PlanView v = plan->view();
+  const size_t pb = wq::static_plane_bytes(v, which);
+  if (pb > wq::kStaticScratchBytes) {
+    char buf[200];
+    std::snprintf(buf, sizeof buf, "one first-contraction plane needs %zu bytes; the static scratch holds %zu",
+                  pb, wq::kStaticScratchBytes);
+    return fail(plan, WQ_ENOSPACE, buf);
+  }
+  hipError_t e = join_rules(plan, stream);
+  if (e != hipSuccess) return hip_fail(plan, e, "wq_assemble_static: join");
+  e = wq::launch_assemble_static(v, which, mass, stiff, stream);
+  if (e != hipSuccess) return hip_fail(plan, e, "wq_assemble_static");
+  return WQ_OK;
+}
+
 wq_status wq_weights(const wq_plan* plan, int dir, int pair, double* w_dev, int32_t* qs_dev,
                      int32_t* qc_dev, hipStream_t stream) {
   if (!plan || dir < 0 || dir >= plan->d || pair < 0 || pair > 3 || !w_dev) return WQ_EINVAL;

@@ -160,3 +160,12 @@ def test_first_contraction_offset_limit():
     st, h = make([ok, ok, thin], p)
     assert st == 0
     _wq.wq_plan_destroy(h)
+
+
+def test_static_scratch_size_matches_header():
+    import re
+    from paper_1605_01238_amd import _wq
+    txt = open(os.path.join(ROOT, "include", "wq.h")).read()
+    m = re.search(r"#define WQ_STATIC_SCRATCH_BYTES \(\(size_t\)(\d+) << (\d+)\)", txt)
+    assert m, "WQ_STATIC_SCRATCH_BYTES not found in wq.h"
+    assert int(m.group(1)) << int(m.group(2)) == _wq.WQ_STATIC_SCRATCH_BYTES
