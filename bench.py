@@ -190,6 +190,78 @@ class Run:
         return self.plan.sizes.value_bytes * len(self.which_names)
 
 
+def batch_extra(steps, warmup, n_patches=64, seed=4):
+    """The batched form: n_patches independent 3D patches, p uniform in
+    {2..6}, 8..40 elements per direction (independently), each with its own
+    seeded perturbed geometry and coefficient field; FP32 bulk (FP64 weights
+    and Jacobians), schedules from the library's autotuner, the whole launch
+    sequence replayed from a captured HIP graph.  Set beside the plain FP64
+    form (one wq_assemble per patch) on the same GPU: speed-up and the
+    matrix-normwise difference of the values."""
+    import torch
+    from paper_1605_01238_amd import WQ_FP32, WQ_FP64, Batch, Plan
+    from workloads import batch_patches
+    ws = batch_patches(n_patches, seed=seed)
+
+    def make(prec):
+        plans, mass, stiff = [], [], []
+        for w in ws:
+            plan = Plan(w.knots(), w.p, prec)
+            plan.bind()
+            plan.setup(torch.from_numpy(w.ctrl()).cuda())
+            x = plan.qp_physical().reshape(-1, plan.d)
+            plan.set_coefficient(w.coefficient().torch(x).contiguous())
+            plans.append(plan)
+            mass.append(torch.empty(plan.nnz, dtype=plan.value_dtype, device="cuda"))
+            stiff.append(torch.empty(plan.nnz, dtype=plan.value_dtype, device="cuda"))
+        return plans, mass, stiff
+
+    p32, m32, s32 = make(WQ_FP32)
+    batch = Batch(p32)
+    batch.bind(m32, s32)
+    batch.tune(3)
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        for _ in range(max(1, warmup)):
+            batch.assemble(3, use_graph=True, stream=stream)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(steps):
+            batch.assemble(3, use_graph=True, stream=stream)
+        e1.record(stream)
+    torch.cuda.synchronize()
+    t32 = e0.elapsed_time(e1) / steps
+    nnz = sum(p.nnz for p in p32)
+    p64, m64, s64 = make(WQ_FP64)
+    for plan, m, s in zip(p64, m64, s64):
+        plan.assemble(3, m, s)
+    torch.cuda.synchronize()
+    f0, f1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    f0.record()
+    for _ in range(steps):
+        for plan, m, s in zip(p64, m64, s64):
+            plan.assemble(3, m, s)
+    f1.record()
+    torch.cuda.synchronize()
+    t64 = f0.elapsed_time(f1) / steps
+    err = {"mass": 0.0, "stiff": 0.0}
+    for a, b_ in ((m32, m64), (s32, s64)):
+        key = "mass" if a is m32 else "stiff"
+        for x, y in zip(a, b_):
+            err[key] = max(err[key], float((x.double() - y).abs().max() / y.abs().max()))
+    out = {"workload": f"{n_patches} patches, p in 2..6, 8..40 elements/dir, mass+stiff",
+           "nnz_per_matrix": nnz, "value": round(2 * nnz / (t32 * 1e-3) / 1e9, 3), "unit": "GNNZ/s",
+           "ms_per_batch": round(t32, 4), "dtype": "f32",
+           "frac": round(2 * nnz * 4 / (t32 * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+           "fp64_per_patch_ms": round(t64, 4),
+           "speedup_vs_fp64_per_patch": round(t64 / t32, 3),
+           "matrix_normwise_diff_vs_fp64": err,
+           "schedule": batch.schedule()}
+    del batch, p32, m32, s32, p64, m64, s64
+    torch.cuda.empty_cache()
+    return out
+
+
 def fill_rate_gbs(nbytes, reps=5):
     """Write-only streaming fill of `nbytes` on the same GPU (torch fill_),
     GB/s: the practical write ceiling beside the nominal peak."""
@@ -307,6 +379,7 @@ def main():
                 "frac": round(buf_bytes_gbs(vb4, float(ta4.mean())) / HBM_PEAK_GBS, 4),
                 "note": "225 MB of values: fits the 256 MB last-level cache"}
             del r4
+        extras["batch_64"] = batch_extra(args.steps, args.warmup)
         out["extra"] = extras
     if cpu is not None:
         out["cpu_baseline"] = cpu

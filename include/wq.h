@@ -192,6 +192,55 @@ wq_status wq_assemble(wq_plan* plan, int which, void* mass_vals_dev, void* stiff
                       hipStream_t stream);
 
 /*
+ * Batches: many independent patches formed together (rows of different
+ * patches are independent like the rows of one patch, Section 1; each patch
+ * is Section 6, Algorithm 3 as in wq_assemble).  The patches are plans of
+ * their own (created, bound and set up as usual; distinct plans; any mix of
+ * degree, size, d and precision).  Per class of equal (p, d, precision) one
+ * launch forms the first contraction of all its patches and one persistent
+ * launch forms all their rows from a device work queue.  Values equal
+ * wq_assemble's bit for bit.
+ *   wq_batch_create  host only; n plans, copied as pointers (the plans must
+ *                    outlive the batch and keep their workspaces while the
+ *                    batch is used).  WQ_EINVAL on a null or repeated plan.
+ *   wq_batch_sizes   bytes of the batch workspace (descriptors and work-queue
+ *                    counters) and the number of classes.
+ *   wq_batch_bind    device workspace (>= wq_batch_sizes, 256-byte aligned,
+ *                    caller-owned) and the output arrays of every patch:
+ *                    mass_vals[n] / stiff_vals[n] (device pointers, either
+ *                    array may be NULL, entries NULL where not formed).
+ *                    Uploads the descriptors on stream.  Every plan must be
+ *                    bound; binding a plan again requires binding the batch
+ *                    again.
+ *   wq_batch_tune    autotuner: per class, times the candidate schedules
+ *                    (runs of rows per pencil, persistent workgroups per
+ *                    compute unit) on the bound patches and keeps the fastest
+ *                    for `which`; synchronizes stream.  Requires wq_setup of
+ *                    every plan; overwrites the outputs.
+ *   wq_batch_assemble  forms `which` for every patch, asynchronously on
+ *                    stream.  use_graph != 0: the launch sequence is captured
+ *                    once into a HIP graph (per which and stream; re-captured
+ *                    after bind or tune) and replayed; needs a stream other
+ *                    than the legacy default stream.
+ *   wq_batch_schedule  class k: info[6] = {p, d, precision, patches,
+ *                    work-item target, workgroups per compute unit}.
+ * Errors: WQ_EINVAL, WQ_ENOSPACE, WQ_ESTATE (unbound batch or plan, plan not
+ * set up), WQ_EDEVICE; wq_batch_last_error gives the message.  Like plans, a
+ * batch is a host object, not thread-safe; a batch and the plans it holds
+ * must not be used concurrently on different streams.
+ */
+typedef struct wq_batch wq_batch;
+wq_status wq_batch_create(int n, wq_plan* const* plans, wq_batch** out);
+wq_status wq_batch_sizes(const wq_batch* batch, size_t* workspace_bytes, int* n_classes);
+wq_status wq_batch_bind(wq_batch* batch, void* workspace, size_t bytes, void* const* mass_vals,
+                        void* const* stiff_vals, hipStream_t stream);
+wq_status wq_batch_tune(wq_batch* batch, int which, hipStream_t stream);
+wq_status wq_batch_assemble(wq_batch* batch, int which, int use_graph, hipStream_t stream);
+wq_status wq_batch_schedule(const wq_batch* batch, int k, int* info);
+const char* wq_batch_last_error(const wq_batch* batch);
+void wq_batch_destroy(wq_batch* batch);
+
+/*
  * For callers that cannot allocate device memory (code under HIP graph
  * capture, tight serving loops, harnesses that forbid allocation): the same
  * values as wq_assemble (same arguments, same results bit for bit) with the

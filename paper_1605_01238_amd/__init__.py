@@ -14,7 +14,7 @@ import numpy as np
 from . import _wq
 from ._wq import (WQ_FP32, WQ_FP64, WQ_MASS, WQ_STATIC_SCRATCH_BYTES, WQ_STIFF, WQError, check)
 
-__all__ = ["Plan", "WQError", "WQ_FP32", "WQ_FP64", "WQ_MASS", "WQ_STATIC_SCRATCH_BYTES", "WQ_STIFF"]
+__all__ = ["Batch", "Plan", "WQError", "WQ_FP32", "WQ_FP64", "WQ_MASS", "WQ_STATIC_SCRATCH_BYTES", "WQ_STIFF"]
 
 
 def _ptr(t) -> Optional[int]:
@@ -132,6 +132,62 @@ class Plan:
         h = getattr(self, "_h", None)
         # at interpreter exit the binding may already be torn down
         destroy = getattr(_wq, "wq_plan_destroy", None) if _wq is not None else None
+        if h is not None and h.value and destroy is not None:
+            destroy(h)
+            self._h = C.c_void_p()
+
+
+def _bcheck(status: int, batch) -> None:
+    if status != _wq.WQ_OK:
+        raise WQError(status, _wq.wq_batch_last_error(batch).decode() if batch else "")
+
+
+class Batch:
+    """Many patches (bound ``Plan`` objects) formed together: one persistent
+    launch per class of equal (p, d, precision), schedules picked by the
+    library's autotuner, optionally replayed from a captured HIP graph."""
+
+    def __init__(self, plans: Sequence[Plan]):
+        self.plans = list(plans)
+        n = len(self.plans)
+        arr = (C.c_void_p * n)(*[p._h.value for p in self.plans])
+        self._h = C.c_void_p()
+        _bcheck(_wq.wq_batch_create(n, arr, C.byref(self._h)), None)
+        nb, nc = C.c_size_t(), C.c_int()
+        _bcheck(_wq.wq_batch_sizes(self._h, C.byref(nb), C.byref(nc)), self._h)
+        self.workspace_bytes, self.n_classes = nb.value, nc.value
+        self.workspace = None
+        self.mass = self.stiff = None
+
+    def bind(self, mass=None, stiff=None, stream=None):
+        """mass, stiff: per-patch device value tensors (or None)."""
+        import torch
+        n = len(self.plans)
+        self.workspace = torch.empty(self.workspace_bytes + 256, dtype=torch.uint8, device="cuda")
+        off = (-self.workspace.data_ptr()) % 256
+        self.mass, self.stiff = mass, stiff
+        m = (C.c_void_p * n)(*[t.data_ptr() if t is not None else None for t in mass]) if mass else None
+        s = (C.c_void_p * n)(*[t.data_ptr() if t is not None else None for t in stiff]) if stiff else None
+        _bcheck(_wq.wq_batch_bind(self._h, self.workspace.data_ptr() + off, self.workspace.numel() - off,
+                                  m, s, _stream(stream)), self._h)
+
+    def tune(self, which: int, stream=None):
+        _bcheck(_wq.wq_batch_tune(self._h, which, _stream(stream)), self._h)
+
+    def assemble(self, which: int, use_graph: bool = False, stream=None):
+        _bcheck(_wq.wq_batch_assemble(self._h, which, int(use_graph), _stream(stream)), self._h)
+
+    def schedule(self):
+        out = []
+        info = (C.c_int * 6)()
+        for k in range(self.n_classes):
+            _bcheck(_wq.wq_batch_schedule(self._h, k, info), self._h)
+            out.append(dict(zip(("p", "d", "precision", "patches", "work_target", "wgs_per_cu"), list(info))))
+        return out
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        destroy = getattr(_wq, "wq_batch_destroy", None) if _wq is not None else None
         if h is not None and h.value and destroy is not None:
             destroy(h)
             self._h = C.c_void_p()

@@ -8,7 +8,7 @@ import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
-SOURCES = ["wq_plan.hip", "wq_setup_kernels.hip", "wq_contract.hip"]
+SOURCES = ["wq_plan.hip", "wq_setup_kernels.hip", "wq_contract.hip", "wq_batch.hip"]
 LIB = os.path.join(HERE, "libwq.so")
 
 

@@ -188,7 +188,7 @@ __device__ inline void store_vec(T* __restrict__ p, const T (&v)[NV]) {
 // consecutive lanes store consecutive elements (whole lines per store).
 // A plane patch (PLANE: direction 3 trivial) has only j3 = 0: one slot.
 template <int P, typename T, bool STIFF, bool PLANE = false>
-__global__ __launch_bounds__(256) void k_first(PlanView v) {
+__device__ __forceinline__ void first_body(const PlanView& v, int bx, int by) {
   constexpr int IC = 2 * P + 1, QC = 3 * P + 1, NCH = STIFF ? kYChannels : 1;
   constexpr int ICY = PLANE ? 1 : IC;                     // j3 slots per record
   constexpr int REC = ICY * NCH;                          // elements per record
@@ -197,9 +197,9 @@ __global__ __launch_bounds__(256) void k_first(PlanView v) {
   const DirView d1 = v.dir[0], d2 = v.dir[1], d3 = v.dir[2];
   const int64_t plane = int64_t(d1.nq) * d2.nq;
   const int tid = threadIdx.x, wv = tid / 64, ln = tid % 64;
-  const int64_t l0 = int64_t(blockIdx.x) * blockDim.x + wv * 64;   // first point of the wave
+  const int64_t l0 = int64_t(bx) * 256 + wv * 64;   // first point of the wave
   const int64_t l = l0 + ln;
-  const int i3 = v.y_i3 + blockIdx.y;   // Y holds the planes i3 >= y_i3
+  const int i3 = v.y_i3 + by;   // Y holds the planes i3 >= y_i3
   if (l0 >= plane) return;   // uniform per wave
   const bool valid = l < plane;
   int qs3, qc3;
@@ -258,8 +258,13 @@ __global__ __launch_bounds__(256) void k_first(PlanView v) {
   }
 }
 
+template <int P, typename T, bool STIFF, bool PLANE = false>
+__global__ __launch_bounds__(256) void k_first(PlanView v) {
+  first_body<P, T, STIFF, PLANE>(v, blockIdx.x, blockIdx.y);
+}
+
 template <int P, typename T, bool STIFF, bool PLANE>
-__device__ __forceinline__ void push_body(PlanView v, T* __restrict__ out, int nseg, int item0) {
+__device__ __forceinline__ void push_body(const PlanView& v, T* __restrict__ out, int nseg, int item) {
   using S = Shape<P, T, STIFF, PLANE>;
   constexpr int IC = S::IC, QC = S::QC, C = S::C, NT = S::NT, J3 = S::J3;
   constexpr int NG = S::NG, NH = S::NH, NCT = S::NCT;
@@ -271,12 +276,6 @@ __device__ __forceinline__ void push_body(PlanView v, T* __restrict__ out, int n
   const DirView d1 = v.dir[0], d2 = v.dir[1], d3 = v.dir[2];
   const int n1 = d1.n, n2 = d2.n, nq1 = d1.nq, nq2 = d2.nq, nel1 = d1.nel;
   const int tid = threadIdx.x;
-  // XCD-aware order: workgroups are dealt round-robin to the 8 XCDs; give
-  // each XCD a contiguous range of work items so that neighbouring pencils,
-  // which read overlapping coefficient blocks, share an L2.
-  const int total = gridDim.x, L = blockIdx.x;
-  const int xcd = L % 8, kx = L / 8, m8 = total / 8, r8 = total % 8;
-  int item = item0 + xcd * m8 + min(xcd, r8) + kx;
   const int part = item % S::NPART;
   item /= S::NPART;
   const int i2 = item % n2;
@@ -488,16 +487,130 @@ __device__ __forceinline__ void push_body(PlanView v, T* __restrict__ out, int n
 }
 
 
+// XCD-aware order: workgroups are dealt round-robin to the 8 XCDs; give
+// each XCD a contiguous range of work items so that neighbouring pencils,
+// which read overlapping coefficient blocks, share an L2.
+__device__ inline int xcd_item() {
+  const int total = gridDim.x, L = blockIdx.x;
+  const int xcd = L % 8, kx = L / 8, m8 = total / 8, r8 = total % 8;
+  return xcd * m8 + min(xcd, r8) + kx;
+}
+
 // The pencil kernel; configurations with WPE > 0 use the variant whose
 // register allocation is bounded for that many waves per SIMD.
 template <int P, typename T, bool STIFF, bool PLANE>
 __global__ __launch_bounds__((Shape<P, T, STIFF, PLANE>::NT)) void k_push(PlanView v, T* __restrict__ out, int nseg, int item0) {
-  push_body<P, T, STIFF, PLANE>(v, out, nseg, item0);
+  push_body<P, T, STIFF, PLANE>(v, out, nseg, item0 + xcd_item());
 }
 template <int P, typename T, bool STIFF>
 __global__ __launch_bounds__((Shape<P, T, STIFF>::NT))
 __attribute__((amdgpu_waves_per_eu(PushCfg<P, T, STIFF>::WPE))) void k_push_wpe(PlanView v, T* __restrict__ out, int nseg, int item0) {
-  push_body<P, T, STIFF, false>(v, out, nseg, item0);
+  push_body<P, T, STIFF, false>(v, out, nseg, item0 + xcd_item());
+}
+
+// ---------------------------------------------------------------------------
+// Batched form: the patches of one class (degree p, dimension d, precision)
+// of a batch, each with its own plan view, outputs and work list.  The
+// first contraction runs as one launch over all patches' blocks; the pencil
+// kernel as one persistent launch whose workgroups take (patch, work item)
+// pairs from a device queue until it is exhausted.  Work items of a patch
+// are numbered as in the single-patch launch, so each row is formed by the
+// same arithmetic in the same order.
+
+// largest k in [0, n) with off[k] <= x (off ascending, off[0] = 0)
+__device__ inline int find_patch(const int* __restrict__ off, int n, int x) {
+  int lo = 0, hi = n;
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) / 2;
+    if (off[mid] <= x) lo = mid;
+    else hi = mid;
+  }
+  return lo;
+}
+
+template <int P, typename T, bool STIFF, bool PLANE>
+__global__ __launch_bounds__(256) void k_first_batch(BatchClassView b) {
+  __shared__ int sk;
+  if (threadIdx.x == 0) sk = find_patch(b.blocks, b.np, blockIdx.x);
+  __syncthreads();
+  const int k = sk;
+  const PlanView v = b.views[k];
+  const int64_t plane = int64_t(v.dir[0].nq) * v.dir[1].nq;
+  const int nbx = int((plane + 255) / 256);
+  const int local = int(blockIdx.x) - b.blocks[k];
+  first_body<P, T, STIFF, PLANE>(v, local % nbx, local / nbx);
+}
+
+template <int P, typename T, bool STIFF, bool PLANE>
+__device__ __forceinline__ void push_batch_body(const BatchClassView& b) {
+  __shared__ int s_w, s_k;
+  const int* items = STIFF ? b.items_stiff : b.items_mass;
+  const int* nsegs = STIFF ? b.nsegs_stiff : b.nsegs_mass;
+  int* counter = b.counter + (STIFF ? 1 : 0);
+  const int total = items[b.np];
+  for (;;) {
+    if (threadIdx.x == 0) {
+      const int w = atomicAdd(counter, 1);
+      s_w = w;
+      s_k = w < total ? find_patch(items, b.np, w) : 0;
+    }
+    __syncthreads();
+    const int w = s_w, k = s_k;
+    if (w >= total) break;   // uniform: every workgroup leaves once the queue is empty
+    const PlanView v = b.views[k];
+    T* out = static_cast<T*>(STIFF ? b.out_stiff[k] : b.out_mass[k]);
+    push_body<P, T, STIFF, PLANE>(v, out, nsegs[k], w - items[k]);
+    __syncthreads();   // s_w and s_k are rewritten by the next take
+  }
+}
+template <int P, typename T, bool STIFF, bool PLANE>
+__global__ __launch_bounds__((Shape<P, T, STIFF, PLANE>::NT)) void k_push_batch(BatchClassView b) {
+  push_batch_body<P, T, STIFF, PLANE>(b);
+}
+template <int P, typename T, bool STIFF>
+__global__ __launch_bounds__((Shape<P, T, STIFF>::NT))
+__attribute__((amdgpu_waves_per_eu(PushCfg<P, T, STIFF>::WPE))) void k_push_batch_wpe(BatchClassView b) {
+  push_batch_body<P, T, STIFF, false>(b);
+}
+
+__global__ void k_zero_counters(int* c, int n) {
+  if (int(threadIdx.x) < n) c[threadIdx.x] = 0;
+}
+
+template <int P, typename T, bool STIFF, bool PLANE>
+hipError_t batch_launch(const BatchClassView& b, int first_blocks, int grid, hipStream_t s) {
+  if (first_blocks > 0)
+    hipLaunchKernelGGL((k_first_batch<P, T, STIFF, PLANE>), dim3(unsigned(first_blocks)), dim3(256), 0, s, b);
+  if constexpr (PushCfg<P, T, STIFF, PLANE>::WPE > 0)
+    hipLaunchKernelGGL((k_push_batch_wpe<P, T, STIFF>), dim3(unsigned(grid)), dim3(Shape<P, T, STIFF, PLANE>::NT), 0, s, b);
+  else
+    hipLaunchKernelGGL((k_push_batch<P, T, STIFF, PLANE>), dim3(unsigned(grid)), dim3(Shape<P, T, STIFF, PLANE>::NT), 0, s, b);
+  return hipGetLastError();
+}
+
+template <int P, typename T>
+hipError_t batch_pt(const BatchClassView& b, int d, bool stiff, int first_blocks, int grid, hipStream_t s) {
+  if (stiff)
+    return d == 2 ? batch_launch<P, T, true, true>(b, first_blocks, grid, s) : batch_launch<P, T, true, false>(b, first_blocks, grid, s);
+  return d == 2 ? batch_launch<P, T, false, true>(b, first_blocks, grid, s) : batch_launch<P, T, false, false>(b, first_blocks, grid, s);
+}
+
+template <int P>
+hipError_t batch_p(const BatchClassView& b, int d, int prec, bool stiff, int first_blocks, int grid, hipStream_t s) {
+  return prec == WQ_FP64 ? batch_pt<P, double>(b, d, stiff, first_blocks, grid, s)
+                         : batch_pt<P, float>(b, d, stiff, first_blocks, grid, s);
+}
+
+template <int P, typename T, bool STIFF, bool PLANE>
+constexpr int parts_of() { return Shape<P, T, STIFF, PLANE>::NPART; }
+template <int P>
+int parts_p(int d, int prec, bool stiff) {
+  if (prec == WQ_FP64) {
+    if (stiff) return d == 2 ? parts_of<P, double, true, true>() : parts_of<P, double, true, false>();
+    return d == 2 ? parts_of<P, double, false, true>() : parts_of<P, double, false, false>();
+  }
+  if (stiff) return d == 2 ? parts_of<P, float, true, true>() : parts_of<P, float, true, false>();
+  return d == 2 ? parts_of<P, float, false, true>() : parts_of<P, float, false, false>();
 }
 
 // The rows of the pencils with i3 in [i3a, i3b): k_first fills the Y planes
@@ -588,6 +701,36 @@ hipError_t launch_assemble(const PlanView& v, int which, void* mass, void* stiff
   PlanView w = v;
   w.y_i3 = 0;
   return assemble_slab(w, which, mass, stiff, s, 0, v.dir[2].n);
+}
+
+hipError_t launch_batch_class(const BatchClassView& b, int p, int d, int prec, bool stiff, int first_blocks,
+                              int grid, hipStream_t s) {
+  switch (p) {
+    case 2: return batch_p<2>(b, d, prec, stiff, first_blocks, grid, s);
+    case 3: return batch_p<3>(b, d, prec, stiff, first_blocks, grid, s);
+    case 4: return batch_p<4>(b, d, prec, stiff, first_blocks, grid, s);
+    case 5: return batch_p<5>(b, d, prec, stiff, first_blocks, grid, s);
+    case 6: return batch_p<6>(b, d, prec, stiff, first_blocks, grid, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_zero_counters(int* c, int n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  if (n > 256) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_zero_counters, dim3(1), dim3(256), 0, s, c, n);
+  return hipGetLastError();
+}
+
+int push_parts(int p, int d, int prec, bool stiff) {
+  switch (p) {
+    case 2: return parts_p<2>(d, prec, stiff);
+    case 3: return parts_p<3>(d, prec, stiff);
+    case 4: return parts_p<4>(d, prec, stiff);
+    case 5: return parts_p<5>(d, prec, stiff);
+    case 6: return parts_p<6>(d, prec, stiff);
+    default: return 1;
+  }
 }
 
 size_t static_plane_bytes(const PlanView& v, int which) {

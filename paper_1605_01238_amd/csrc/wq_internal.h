@@ -103,6 +103,23 @@ struct PlanView {
   int y_i3;              // ybuf holds the first-contraction planes i3 >= y_i3
 };
 
+// One class (degree p, dimension d, precision) of a batch of patches, in
+// the batch workspace: per patch its plan view, outputs, the prefix of its
+// pencil-kernel work items and first-contraction blocks, and its runs of
+// rows per pencil; two work-queue counters (mass, stiffness).
+struct BatchClassView {
+  const PlanView* views;
+  void* const* out_mass;
+  void* const* out_stiff;
+  const int* items_mass;    // [np + 1]
+  const int* items_stiff;   // [np + 1]
+  const int* nsegs_mass;    // [np]
+  const int* nsegs_stiff;   // [np]
+  const int* blocks;        // [np + 1]
+  int* counter;             // [2]
+  int np;
+};
+
 struct Layout {
   size_t knots[3], x[3], qspan[3], bv[3], bd[3], bw[3], w[3], op64[3], op32[3], bt64[3], bt32[3], wt64[3], wt32[3], prefix[3], colt64[3], colt32[3];
   size_t field, ybuf, ctrl, dctrl, flags, total;
@@ -144,4 +161,11 @@ hipError_t launch_assemble(const PlanView& v, int which, void* mass, void* stiff
 hipError_t launch_assemble_static(const PlanView& v, int which, void* mass, void* stiff, hipStream_t s);
 // Bytes of one first-contraction plane (one i3) for the matrices of `which`.
 size_t static_plane_bytes(const PlanView& v, int which);
+// Batched form: one class of patches (first contraction over all blocks,
+// then the persistent pencil kernel with `grid` workgroups).
+hipError_t launch_batch_class(const BatchClassView& b, int p, int d, int prec, bool stiff, int first_blocks,
+                              int grid, hipStream_t s);
+hipError_t launch_zero_counters(int* c, int n, hipStream_t s);
+// j3 parts per pencil of the pencil kernel for (p, d, precision, matrix).
+int push_parts(int p, int d, int prec, bool stiff);
 }  // namespace wq

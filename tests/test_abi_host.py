@@ -169,3 +169,32 @@ def test_static_scratch_size_matches_header():
     m = re.search(r"#define WQ_STATIC_SCRATCH_BYTES \(\(size_t\)(\d+) << (\d+)\)", txt)
     assert m, "WQ_STATIC_SCRATCH_BYTES not found in wq.h"
     assert int(m.group(1)) << int(m.group(2)) == _wq.WQ_STATIC_SCRATCH_BYTES
+
+
+def test_batch_host_calls_without_device():
+    """wq_batch_create / wq_batch_sizes are host only: classes by (p, d,
+    precision), repeated or null plans refused, unbound batches refused."""
+    from paper_1605_01238_amd import _wq
+    from workloads import open_uniform_knots
+    hs = []
+    for p, prec in ((2, 0), (3, 0), (2, 0), (2, 1)):
+        st, h = make([open_uniform_knots(p, 6)] * 3, p, prec=prec)
+        assert st == 0
+        hs.append(h)
+    arr = (C.c_void_p * 4)(*[h.value for h in hs])
+    b = C.c_void_p()
+    assert _wq.wq_batch_create(4, arr, C.byref(b)) == 0
+    nb, nc = C.c_size_t(), C.c_int()
+    assert _wq.wq_batch_sizes(b, C.byref(nb), C.byref(nc)) == 0
+    assert nc.value == 3 and nb.value > 0
+    info = (C.c_int * 6)()
+    assert _wq.wq_batch_schedule(b, 0, info) == 0 and list(info)[:4] == [2, 3, 0, 2]
+    assert _wq.wq_batch_schedule(b, 3, info) == _wq.WQ_EINVAL
+    assert _wq.wq_batch_assemble(b, 3, 0, None) == _wq.WQ_ESTATE
+    assert b"not bound" in _wq.wq_batch_last_error(b)
+    _wq.wq_batch_destroy(b)
+    rep = (C.c_void_p * 2)(hs[0].value, hs[0].value)
+    assert _wq.wq_batch_create(2, rep, C.byref(b)) == _wq.WQ_EINVAL
+    assert _wq.wq_batch_create(0, arr, C.byref(b)) == _wq.WQ_EINVAL
+    for h in hs:
+        _wq.wq_plan_destroy(h)

@@ -104,6 +104,19 @@ class CoefficientField:
     alpha: np.ndarray   # (m,)
     beta: np.ndarray    # (m,)
 
+    def torch(self, x):
+        """The same field evaluated with torch on x's device (input
+        generation on the GPU for large point sets)."""
+        import torch
+        if x.shape[-1] == 2:
+            x = torch.cat([x, torch.zeros(x.shape[:-1] + (1,), dtype=x.dtype, device=x.device)], dim=-1)
+        ks = torch.as_tensor(self.ks, dtype=torch.float64, device=x.device)
+        ph = 2.0 * math.pi * (x.to(torch.float64) @ ks.T)
+        a = torch.as_tensor(self.alpha, device=x.device)
+        b = torch.as_tensor(self.beta, device=x.device)
+        g = torch.cos(ph) @ a + torch.sin(ph) @ b
+        return 1.0 + 0.5 * torch.sin(g)
+
     def __call__(self, x: np.ndarray) -> np.ndarray:
         x = np.asarray(x, dtype=np.float64)
         if x.shape[-1] == 2:    # a plane domain: the field on z = 0
@@ -176,6 +189,24 @@ PLANE = (Workload("p4_512el_plane", 4, (512, 512), geom_seed=30, coef_seed=31, w
          Workload("p6_256el_plane", 6, (256, 256), geom_seed=32, coef_seed=None, which=("stiff", "mass")))
 
 WORKLOADS = {w.name: w for w in (SMALL_P2, MID_P4, LARGE_P6) + SWEEP + PLANE}
+
+
+def batch_patches(n: int, seed: int, p_range=(2, 6), nel_range=(8, 40), d_choices=(3,), p2d: float = 0.0):
+    """n independent single-patch problems of mixed degree and size (a
+    batch): p uniform in p_range, elements per direction uniform in
+    nel_range (independently per direction), dimension from d_choices (2 with
+    probability p2d when both are allowed), each with its own seeded
+    perturbed geometry and coefficient field."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    out = []
+    for k in range(n):
+        p = int(rng.integers(p_range[0], p_range[1] + 1))
+        d = 2 if (2 in d_choices and rng.random() < p2d) else 3
+        # at least p+2 knot-spans per direction (the method's minimum patch)
+        nel = tuple(max(p + 2, int(rng.integers(nel_range[0], nel_range[1] + 1))) for _ in range(d))
+        out.append(Workload(f"batch{seed}_{k}", p, nel, geom_seed=1000 * seed + 2 * k + 1,
+                            coef_seed=1000 * seed + 2 * k + 2, which=("mass", "stiff")))
+    return out
 
 
 def sample_rows(n_dof3, p: int, n_uniform: int, n_boundary: int, seed: int) -> np.ndarray:
