@@ -262,6 +262,44 @@ def batch_extra(steps, warmup, n_patches=64, seed=4):
     return out
 
 
+def serving_extra(n_requests=2000, n_geoms=16, seed=5):
+    """The serving loop: n_geoms resident geometries (p uniform in {2..6},
+    8..48 elements per direction, 2D with probability 0.3), each set up once
+    (weights, det J, J^{-1}, pattern resident); n_requests requests, each a
+    new seeded coefficient field on one of them (stiffness, FP32 bulk),
+    arriving as a seeded Poisson stream; continuous batching over 4 streams
+    with at most 32 requests and 32 GiB in flight.  First all requests at
+    once (capacity), then Poisson rates of 0.5 and 0.8 of that capacity."""
+    import torch
+    from paper_1605_01238_amd import WQ_FP32, WQ_STIFF
+    from paper_1605_01238_amd.serving import Geometry, Server, poisson_requests, summarize
+    from workloads import batch_patches, coefficient_field
+    ws = batch_patches(n_geoms, seed=seed, nel_range=(8, 48), d_choices=(2, 3), p2d=0.3)
+    geoms = [Geometry(w.knots(), w.p, w.ctrl(), WQ_FP32, WQ_STIFF) for w in ws]
+
+    def coef(req, xq):
+        return coefficient_field(req.coef_seed).torch(xq).contiguous()
+
+    srv = Server(geoms, coef, n_streams=4, max_inflight=32, hbm_budget=32 << 30)
+    srv.run(poisson_requests(64, 0.0, n_geoms, seed + 1))          # warm-up
+    torch.cuda.synchronize()
+    cap = summarize(srv.run(poisson_requests(n_requests, 0.0, n_geoms, seed + 2)))
+    runs = {"all_at_once": cap}
+    for frac in (0.5, 0.8):
+        rate = frac * cap["requests_per_s"]
+        runs[f"poisson_{frac}x"] = dict(summarize(srv.run(poisson_requests(n_requests, rate, n_geoms,
+                                                                         seed + 3))),
+                                        rate_per_s=round(rate, 1))
+    torch.cuda.synchronize()
+    out = {"workload": f"{n_requests} requests on {n_geoms} resident geometries (p 2..6, 8..48 el/dir, "
+                       f"30% 2D), new coefficient each, stiffness, FP32 bulk",
+           "geometries": [(w.p, list(w.n_el)) for w in ws], "runs": runs,
+           "peak_inflight": srv.peak_inflight, "peak_gib_inflight": round(srv.peak_bytes / 2**30, 2)}
+    del srv, geoms
+    torch.cuda.empty_cache()
+    return out
+
+
 def fill_rate_gbs(nbytes, reps=5):
     """Write-only streaming fill of `nbytes` on the same GPU (torch fill_),
     GB/s: the practical write ceiling beside the nominal peak."""
@@ -380,6 +418,10 @@ def main():
                 "note": "225 MB of values: fits the 256 MB last-level cache"}
             del r4
         extras["batch_64"] = batch_extra(args.steps, args.warmup)
+        extras["serving"] = serving_extra()
+        sv = extras["serving"]["runs"]["poisson_0.8x"]
+        out["latency_ms"]["serving_p50"] = sv["latency_ms_p50"]
+        out["latency_ms"]["serving_p99"] = sv["latency_ms_p99"]
         out["extra"] = extras
     if cpu is not None:
         out["cpu_baseline"] = cpu

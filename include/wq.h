@@ -192,6 +192,29 @@ wq_status wq_assemble(wq_plan* plan, int which, void* mass_vals_dev, void* stiff
                       hipStream_t stream);
 
 /*
+ * Requests: the matrices of a plan for a new diffusion coefficient a(x) on
+ * its resident geometry (weights, operators, det J and J^{-1} of the last
+ * wq_setup), formed into a caller-owned request context instead of the
+ * plan's workspace, so that requests on one plan may run concurrently on
+ * different streams (each with its own context and outputs; they only read
+ * the plan).  Same method as wq_set_coefficient + wq_assemble (Section 3,
+ * eq. coef_stiff times a; Section 6, Algorithm 3): the coefficients are the
+ * plan's a = 1 field with K multiplied by a(x_q).
+ *   wq_request_bytes     bytes of one request context.
+ *   wq_assemble_request  ctx: device, >= wq_request_bytes, 256-byte aligned,
+ *                        caller-owned, contents overwritten; coef_dev as in
+ *                        wq_setup (NULL: a = 1); which, mass_vals_dev,
+ *                        stiff_vals_dev as in wq_assemble.  Asynchronous on
+ *                        stream.  The plan's field must be that of a = 1
+ *                        (its last wq_setup or wq_set_coefficient had a NULL
+ *                        coefficient), else WQ_ESTATE.
+ * Errors: WQ_EINVAL, WQ_ESTATE, WQ_ENOSPACE, WQ_EDEVICE.
+ */
+wq_status wq_request_bytes(const wq_plan* plan, size_t* bytes);
+wq_status wq_assemble_request(wq_plan* plan, void* ctx, size_t ctx_bytes, const double* coef_dev, int which,
+                              void* mass_vals_dev, void* stiff_vals_dev, hipStream_t stream);
+
+/*
  * Batches: many independent patches formed together (rows of different
  * patches are independent like the rows of one patch, Section 1; each patch
  * is Section 6, Algorithm 3 as in wq_assemble).  The patches are plans of

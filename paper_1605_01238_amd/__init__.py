@@ -110,6 +110,28 @@ class Plan:
                               _ptr(stiff) if which & WQ_STIFF else None, _stream(stream)), self._h)
         return mass, stiff
 
+    def request_bytes(self) -> int:
+        n = C.c_size_t()
+        check(_wq.wq_request_bytes(self._h, C.byref(n)), self._h)
+        return n.value
+
+    def assemble_request(self, ctx, coef, which: int, mass=None, stiff=None, stream=None):
+        """Matrices for coefficient ``coef`` (device float64, n_qp_total, or
+        None for a = 1) into a request context ``ctx`` (device uint8 tensor
+        of at least request_bytes() + 256 bytes)."""
+        import torch
+        if coef is not None and coef.numel() != self.n_qp_total:
+            raise ValueError(f"coefficient must hold {self.n_qp_total} values")
+        if (which & WQ_MASS) and mass is None:
+            mass = torch.empty(self.nnz, dtype=self.value_dtype, device="cuda")
+        if (which & WQ_STIFF) and stiff is None:
+            stiff = torch.empty(self.nnz, dtype=self.value_dtype, device="cuda")
+        off = (-ctx.data_ptr()) % 256
+        check(_wq.wq_assemble_request(self._h, ctx.data_ptr() + off, ctx.numel() - off, _ptr(coef), which,
+                                      _ptr(mass) if which & WQ_MASS else None,
+                                      _ptr(stiff) if which & WQ_STIFF else None, _stream(stream)), self._h)
+        return mass, stiff
+
     def weights(self, d: int, pair: int, stream=None):
         import torch
         qcap = 3 * self.p + 1

@@ -42,6 +42,8 @@ SIGNATURES = [
     ("wq_pattern", C.c_int, [_P, _P, _P, _P]),
     ("wq_assemble", C.c_int, [_P, C.c_int, _P, _P, _P]),
     ("wq_assemble_static", C.c_int, [_P, C.c_int, _P, _P, _P]),
+    ("wq_request_bytes", C.c_int, [_P, C.POINTER(C.c_size_t)]),
+    ("wq_assemble_request", C.c_int, [_P, _P, C.c_size_t, _P, C.c_int, _P, _P, _P]),
     ("wq_batch_create", C.c_int, [C.c_int, C.POINTER(_P), C.POINTER(_P)]),
     ("wq_batch_sizes", C.c_int, [_P, C.POINTER(C.c_size_t), C.POINTER(C.c_int)]),
     ("wq_batch_bind", C.c_int, [_P, _P, C.c_size_t, C.POINTER(_P), C.POINTER(_P), _P]),

@@ -136,6 +136,7 @@ struct wq_plan {
   char* ws = nullptr;
   size_t ws_bytes = 0;
   bool bound = false, setup_done = false;
+  bool unit_coef = false;   // the field holds the coefficients of a = 1 (requests scale it)
   std::string err;
   // The univariate stage runs on a second stream, forked from the caller's
   // stream at wq_setup and joined by the calls that read its tables.
@@ -155,6 +156,8 @@ hipError_t launch_ctrl_diff(const PlanView& v, const double* ctrl, hipStream_t s
 hipError_t launch_geometry(const PlanView& v, const double* coef, double* xphys_out, hipStream_t s);
 hipError_t launch_pattern(const PlanView& v, int64_t* row_ptr, int32_t* col_idx, hipStream_t s);
 hipError_t launch_qranges(const PlanView& v, int dir, int32_t* q_start, int32_t* q_count, hipStream_t s);
+// field_out = the plan's field with channels K (1..6) multiplied by a(x_q).
+hipError_t launch_scale_field(const PlanView& v, const double* coef, void* field_out, hipStream_t s);
 hipError_t launch_assemble(const PlanView& v, int which, void* mass, void* stiff, hipStream_t s);
 // The same rows with the first-contraction buffer in the library's static
 // scratch, i3 plane slab by slab (no allocation of any kind).

@@ -310,6 +310,7 @@ wq_status wq_setup(wq_plan* plan, const double* ctrl_dev, const double* coef_dev
   e = wq::launch_geometry(v, coef_dev, nullptr, stream);
   if (e != hipSuccess) return hip_fail(plan, e, "wq_setup: geometry kernel");
   plan->setup_done = true;
+  plan->unit_coef = coef_dev == nullptr;
   return WQ_OK;
 }
 
@@ -318,6 +319,51 @@ wq_status wq_set_coefficient(wq_plan* plan, const double* coef_dev, hipStream_t 
   if (!plan->setup_done) return fail(plan, WQ_ESTATE, "wq_set_coefficient before wq_setup");
   hipError_t e = wq::launch_geometry(plan->view(), coef_dev, nullptr, stream);
   if (e != hipSuccess) return hip_fail(plan, e, "wq_set_coefficient: geometry kernel");
+  plan->unit_coef = coef_dev == nullptr;
+  return WQ_OK;
+}
+
+// Request context: the coefficient field and the first-contraction buffer.
+static void request_layout(const wq_plan* plan, size_t* field_off, size_t* y_off, size_t* total) {
+  const size_t elem = plan->prec == WQ_FP64 ? 8 : 4;
+  const size_t fbytes = size_t(wq::kNumChannels) * size_t(plan->nqtot) * elem;
+  const size_t ybytes = size_t(plan->n[2]) * size_t(plan->nq[1]) * size_t(plan->nq[0]) *
+                        (plan->d == 3 ? size_t(wq::icap_of(plan->p)) : 1) * wq::kYChannels * elem;
+  *field_off = 0;
+  *y_off = align256(fbytes);
+  *total = *y_off + align256(ybytes);
+}
+
+wq_status wq_request_bytes(const wq_plan* plan, size_t* bytes) {
+  if (!plan || !bytes) return WQ_EINVAL;
+  size_t f, y;
+  request_layout(plan, &f, &y, bytes);
+  return WQ_OK;
+}
+
+wq_status wq_assemble_request(wq_plan* plan, void* ctx, size_t ctx_bytes, const double* coef_dev, int which,
+                              void* mass, void* stiff, hipStream_t stream) {
+  if (!plan) return WQ_EINVAL;
+  if (!ctx) return fail(plan, WQ_EINVAL, "null request context");
+  if (which <= 0 || (which & ~(WQ_MASS | WQ_STIFF))) return fail(plan, WQ_EINVAL, "which must be WQ_MASS, WQ_STIFF or both");
+  if ((which & WQ_MASS) && !mass) return fail(plan, WQ_EINVAL, "null mass output");
+  if ((which & WQ_STIFF) && !stiff) return fail(plan, WQ_EINVAL, "null stiffness output");
+  if (!plan->setup_done) return fail(plan, WQ_ESTATE, "wq_assemble_request before wq_setup");
+  if (!plan->unit_coef) return fail(plan, WQ_ESTATE, "wq_assemble_request needs the plan's field for a = 1 (set up or set with a NULL coefficient)");
+  size_t f, y, total;
+  request_layout(plan, &f, &y, &total);
+  if (ctx_bytes < total) return fail(plan, WQ_ENOSPACE, "request context smaller than wq_request_bytes()");
+  if (reinterpret_cast<uintptr_t>(ctx) % 256 != 0) return fail(plan, WQ_ENOSPACE, "request context must be 256-byte aligned");
+  hipError_t e = join_rules(plan, stream);
+  if (e != hipSuccess) return hip_fail(plan, e, "wq_assemble_request: join");
+  wq::PlanView v = plan->view();
+  char* c = static_cast<char*>(ctx);
+  e = wq::launch_scale_field(v, coef_dev, c + f, stream);
+  if (e != hipSuccess) return hip_fail(plan, e, "wq_assemble_request: coefficient field");
+  v.field = c + f;
+  v.ybuf = c + y;
+  e = wq::launch_assemble(v, which, mass, stiff, stream);
+  if (e != hipSuccess) return hip_fail(plan, e, "wq_assemble_request: contraction kernel");
   return WQ_OK;
 }
 

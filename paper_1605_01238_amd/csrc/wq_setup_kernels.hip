@@ -488,6 +488,20 @@ __global__ void k_prefix(PlanView v) {
   }
 }
 
+// Coefficient field of a request: the plan's field for a = 1 (det J and
+// K = det J J^{-1} J^{-T}) with K multiplied by the diffusion coefficient
+// a(x_q) (eq. coef_stiff times a); det J (eq. mass2) is copied.
+template <typename T>
+__global__ __launch_bounds__(256) void k_scale_field(const T* __restrict__ in, const double* __restrict__ a,
+                                                     T* __restrict__ out, int64_t n) {
+  const int64_t q = int64_t(blockIdx.x) * 256 + threadIdx.x;
+  if (q >= n) return;
+  const double aq = a ? a[q] : 1.0;
+  out[q] = in[q];
+#pragma unroll
+  for (int c = 1; c < kNumChannels; ++c) out[c * n + q] = T(double(in[c * n + q]) * aq);
+}
+
 // Q_i = [q_start[i], q_start[i] + q_count[i]) of one direction (either
 // output may be null).
 __global__ void k_qranges(PlanView v, int dir, int32_t* __restrict__ q_start, int32_t* __restrict__ q_count) {
@@ -887,6 +901,17 @@ hipError_t launch_geometry(const PlanView& v, const double* coef, double* xphys,
 #define C(P) geometry_p<P>(v, coef, xphys, s)
   WQ_DISPATCH_P(v.p, C)
 #undef C
+}
+
+hipError_t launch_scale_field(const PlanView& v, const double* coef, void* field_out, hipStream_t s) {
+  const unsigned blocks = unsigned((v.nqtot + 255) / 256);
+  if (v.prec == WQ_FP64)
+    hipLaunchKernelGGL((k_scale_field<double>), dim3(blocks), dim3(256), 0, s, static_cast<const double*>(v.field), coef,
+                       static_cast<double*>(field_out), v.nqtot);
+  else
+    hipLaunchKernelGGL((k_scale_field<float>), dim3(blocks), dim3(256), 0, s, static_cast<const float*>(v.field), coef,
+                       static_cast<float*>(field_out), v.nqtot);
+  return hipGetLastError();
 }
 
 hipError_t launch_qranges(const PlanView& v, int dir, int32_t* q_start, int32_t* q_count, hipStream_t s) {
