@@ -24,7 +24,8 @@ and no boundary conditions.
   for affine maps and constant coefficients, used by the exactness pins.
 
 The same definitions in d = 2 (two directions, d^2 = 4 stiffness terms) are
-taken when two knot vectors are given.
+taken when two knot vectors are given, and in d = 1 (one direction, one
+stiffness term with K = a / J: the problem of Section 7.1) when one is.
 
 Pins (tests/test_oracle_assembly.py): direct == sum-factorized (the identity
 between eq:massquadrature and eq:sumfactorization), affine exactness against
@@ -37,8 +38,8 @@ from typing import Callable, Optional, Sequence
 
 import numpy as np
 
-from .geometry import (coefficients_from_jacobian, coefficients_from_jacobian_2d, map_and_jacobian,
-                       map_and_jacobian_2d)
+from .geometry import (coefficients_from_jacobian, coefficients_from_jacobian_1d, coefficients_from_jacobian_2d,
+                       map_and_jacobian, map_and_jacobian_1d, map_and_jacobian_2d)
 from .rules import rules_for
 
 
@@ -48,14 +49,14 @@ def mode_product(X: np.ndarray, A: np.ndarray, m: int) -> np.ndarray:
 
 
 class Problem:
-    """One single-patch problem in d = 3 (or d = 2) dimensions: knots,
-    degree, control net, coefficient."""
+    """One single-patch problem in d = 3 (or d = 2, or d = 1) dimensions:
+    knots, degree, control net, coefficient."""
 
     def __init__(self, knots3: Sequence, p: int, ctrl: np.ndarray,
                  coef: Optional[Callable[[np.ndarray], np.ndarray]] = None):
         d = len(knots3)
-        if d not in (2, 3):
-            raise ValueError("2D or 3D problems only")
+        if d not in (1, 2, 3):
+            raise ValueError("1D, 2D or 3D problems only")
         self.d = d
         self.p = p
         self.knots3 = [np.asarray(k, dtype=np.float64) for k in knots3]
@@ -116,10 +117,13 @@ class Problem:
     def _geometry(self, X):
         if self.d == 3:
             return map_and_jacobian(self.knots3, self.p, self.ctrl, X[0], X[1], X[2])
-        return map_and_jacobian_2d(self.knots3, self.p, self.ctrl, X[0], X[1])
+        if self.d == 2:
+            return map_and_jacobian_2d(self.knots3, self.p, self.ctrl, X[0], X[1])
+        return map_and_jacobian_1d(self.knots3, self.p, self.ctrl, X[0])
 
     def _coefficients(self, J, a):
-        return coefficients_from_jacobian(J, a) if self.d == 3 else coefficients_from_jacobian_2d(J, a)
+        return {3: coefficients_from_jacobian, 2: coefficients_from_jacobian_2d,
+                1: coefficients_from_jacobian_1d}[self.d](J, a)
 
     def _fields_on(self, X):
         F, J = self._geometry(X)
@@ -172,8 +176,10 @@ class Problem:
             if method == "direct":
                 if d == 3:
                     v = np.einsum("ax,by,cz,xyz->abc", T[0], T[1], T[2], field, optimize=False)
-                else:
+                elif d == 2:
                     v = np.einsum("ax,by,xy->ab", T[0], T[1], field, optimize=False)
+                else:
+                    v = np.einsum("ax,x->a", T[0], field, optimize=False)
             elif method == "sumfact":
                 v = field
                 for k in reversed(range(d)):
@@ -212,8 +218,10 @@ class Problem:
         det, K = det.astype(np.float64), K.astype(np.float64)
         if d == 3:
             Wq = wts[0][:, None, None] * wts[1][None, :, None] * wts[2][None, None, :]
-        else:
+        elif d == 2:
             Wq = wts[0][:, None] * wts[1][None, :]
+        else:
+            Wq = wts[0]
         # dense basis tables at Gauss points
         from .splines import basis_and_derivs
         tabs = []
@@ -228,8 +236,10 @@ class Problem:
             A = [tabs[k][dirs_deriv[k]] for k in range(d)]
             if d == 3:
                 T = np.einsum("ix,jy,kz->kjixyz", A[0], A[1], A[2])
-            else:
+            elif d == 2:
                 T = np.einsum("ix,jy->jixy", A[0], A[1])
+            else:
+                T = A[0]
             return T.reshape(N, -1)
         if which == "mass":
             P0 = phi((0,) * d)

@@ -19,7 +19,10 @@ points) the univariate B-spline values and derivatives are exact rationals
 before conversion.  Results are rounded to FP64 by the callers.
 
 The 2D forms (``map_and_jacobian_2d``, ``coefficients_from_jacobian_2d``)
-follow the same definitions with (p+1)^2 functions per point and a 2x2 J.
+follow the same definitions with (p+1)^2 functions per point and a 2x2 J;
+the 1D forms (``map_and_jacobian_1d``, ``coefficients_from_jacobian_1d``)
+with p+1 functions per point, J = dF/dzeta, det J = J and K = a / J (the
+one-direction case of eq. coef_stiff, as in the problem of Section 7.1).
 
 Pins (tests/test_oracle_geometry.py): Greville control points give the
 identity map (J = I, K = I); an affine control net gives J = A everywhere;
@@ -166,6 +169,30 @@ def coefficients_from_jacobian_2d(J: np.ndarray, a: Optional[np.ndarray] = None)
     adj = np.stack([np.stack([j[..., 1, 1], -j[..., 0, 1]], -1),
                     np.stack([-j[..., 1, 0], j[..., 0, 0]], -1)], -2)
     K = np.einsum("...ik,...jk->...ij", adj, adj) / det[..., None, None]
+    if a is not None:
+        K = K * np.asarray(a)[..., None, None]
+    return det, K
+
+
+def map_and_jacobian_1d(knots1, p: int, ctrl: np.ndarray, X1):
+    """F and J = dF/dzeta of a univariate map at the points X1.
+
+    ctrl: (n1, 1) control points.  Returns F with shape (len(X1), 1) and J
+    with shape (len(X1), 1, 1), in longdouble."""
+    ctrl = np.asarray(ctrl).astype(LD)[:, 0]
+    f1, V1, D1 = local_basis(knots1[0], p, X1)
+    i1 = f1[:, None] + np.arange(p + 1)[None, :]
+    C = ctrl[i1]                                   # (n_pts, p+1)
+    F = (V1 * C).sum(axis=1)
+    J = (D1 * C).sum(axis=1)
+    return F[:, None], J[:, None, None]
+
+
+def coefficients_from_jacobian_1d(J: np.ndarray, a: Optional[np.ndarray] = None):
+    """1D forms of eq. mass2 and eq. coef_stiff: c = J and K = a / J.
+    Returns (J[...], K[..., 1, 1])."""
+    det = J[..., 0, 0]
+    K = 1 / J
     if a is not None:
         K = K * np.asarray(a)[..., None, None]
     return det, K

@@ -59,8 +59,8 @@ def greville(knots: np.ndarray, p: int) -> np.ndarray:
 def control_net(knots3, p: int, seed: Optional[int], amp_h: float = 0.05,
                 twist_deg: float = 0.0, affine: Optional[np.ndarray] = None,
                 shift: Optional[np.ndarray] = None) -> np.ndarray:
-    """Control net of a trivariate (or, given two knot vectors, bivariate)
-    spline map on the given knots.
+    """Control net of a trivariate (or, given two knot vectors, bivariate;
+    given one, univariate) spline map on the given knots.
 
     Recipe: Greville points (identity map); optionally an affine map
     x -> A x + s; optionally (3D only) a twist of the (x, y) coordinates
@@ -68,9 +68,15 @@ def control_net(knots3, p: int, seed: Optional[int], amp_h: float = 0.05,
     ``twist_deg`` degrees at z = 1; then a seeded uniform perturbation
     U(-amp_h*h, amp_h*h) of every coordinate of every control point, h being
     the smallest span length.  ``seed=None`` disables the perturbation.
-    Returns float64 of shape (n3, n2, n1, 3), or (n2, n1, 2) in 2D."""
+    Returns float64 of shape (n3, n2, n1, 3), (n2, n1, 2) in 2D or (n1, 1)
+    in 1D (a 1D perturbation below h/(2p) keeps the points increasing, so
+    that J > 0)."""
     g = [greville(np.asarray(k, dtype=np.float64), p) for k in knots3]
-    if len(g) == 2:
+    if len(g) == 1:
+        if twist_deg:
+            raise ValueError("the twist is defined for 3D nets only")
+        P = g[0][:, None].astype(np.float64)
+    elif len(g) == 2:
         if twist_deg:
             raise ValueError("the twist is defined for 3D nets only")
         X2, X1 = np.meshgrid(g[1], g[0], indexing="ij")
@@ -96,6 +102,38 @@ def control_net(knots3, p: int, seed: Optional[int], amp_h: float = 0.05,
     return np.ascontiguousarray(P, dtype=np.float64)
 
 
+def arcsin_curve_net(knots: np.ndarray, p: int) -> np.ndarray:
+    """Control points of the curve map of the 1D test problem (the inverse
+    of t = 2 sin x: x(t) = arcsin(t / 2), t in [0, 1], x in [0, pi/6]).
+
+    Recipe: the de Boor-Fix dual functionals applied to the degree-p Taylor
+    polynomial of x at the Greville abscissa g_i,
+        C_i = (1/p!) sum_r (-1)^r psi_i^(p-r)(g_i) x^(r)(g_i),
+        psi_i(y) = prod_{j=1..p} (y - xi_{i+j}),
+    a local quasi-interpolant that reproduces polynomials of degree p and
+    approximates x to O(h^{p+1}) (O(h^{p+1-k}) in the k-th derivative), and
+    keeps both end points.  The derivatives come in closed form:
+    x' = (4 - t^2)^{-1/2} and x^(k+1) = P_k(t) (4 - t^2)^{-1/2-k} with
+    P_0 = 1, P_{k+1} = (4 - t^2) P_k' + (2k + 1) t P_k.
+    Returns float64 (n1, 1)."""
+    kn = np.asarray(knots, dtype=np.float64)
+    n = kn.size - p - 1
+    g = greville(kn, p)
+    polys = [np.polynomial.Polynomial([1.0])]
+    four = np.polynomial.Polynomial([4.0, 0.0, -1.0])
+    tpoly = np.polynomial.Polynomial([0.0, 1.0])
+    for k in range(p):
+        Pk = polys[-1]
+        polys.append(four * Pk.deriv() + (2 * k + 1) * tpoly * Pk)
+    C = np.empty((n, 1))
+    for i in range(n):
+        t = g[i]
+        deriv = [math.asin(t / 2.0)] + [polys[k](t) * (4.0 - t * t) ** (-0.5 - k) for k in range(p)]
+        psi = np.polynomial.Polynomial.fromroots(kn[i + 1:i + p + 1])
+        C[i, 0] = sum((-1) ** r * psi.deriv(p - r)(t) * deriv[r] for r in range(p + 1)) / math.factorial(p)
+    return np.ascontiguousarray(C)
+
+
 @dataclasses.dataclass(frozen=True)
 class CoefficientField:
     """a(x) = 1 + 0.5 sin(g(x)), g a low-frequency Fourier sum with seeded
@@ -108,8 +146,8 @@ class CoefficientField:
         """The same field evaluated with torch on x's device (input
         generation on the GPU for large point sets)."""
         import torch
-        if x.shape[-1] == 2:
-            x = torch.cat([x, torch.zeros(x.shape[:-1] + (1,), dtype=x.dtype, device=x.device)], dim=-1)
+        if x.shape[-1] < 3:
+            x = torch.cat([x, torch.zeros(x.shape[:-1] + (3 - x.shape[-1],), dtype=x.dtype, device=x.device)], dim=-1)
         ks = torch.as_tensor(self.ks, dtype=torch.float64, device=x.device)
         ph = 2.0 * math.pi * (x.to(torch.float64) @ ks.T)
         a = torch.as_tensor(self.alpha, device=x.device)
@@ -119,8 +157,8 @@ class CoefficientField:
 
     def __call__(self, x: np.ndarray) -> np.ndarray:
         x = np.asarray(x, dtype=np.float64)
-        if x.shape[-1] == 2:    # a plane domain: the field on z = 0
-            x = np.concatenate([x, np.zeros(x.shape[:-1] + (1,))], axis=-1)
+        if x.shape[-1] < 3:    # a plane or a line: the field on z = 0 (and y = 0)
+            x = np.concatenate([x, np.zeros(x.shape[:-1] + (3 - x.shape[-1],))], axis=-1)
         ph = 2.0 * math.pi * (x @ self.ks.T.astype(np.float64))
         g = np.cos(ph) @ self.alpha + np.sin(ph) @ self.beta
         return 1.0 + 0.5 * np.sin(g)
