@@ -97,9 +97,13 @@ typedef struct {
 
 /*
  * Create a plan (host only; no device work).
- *   d          3, or 2 for a plane patch (Section 3 with two directions);
- *              a 2D plan reports n[2] = n_qp[2] = 1 and forms the 2D rows,
- *              of length #I_i1 #I_i2, with the same calls.
+ *   d          3; 2 for a plane patch, 1 for a curve (Section 3 with two
+ *              or one direction; Section 7.1 for d = 1).  A plan of d < 3
+ *              reports n[k] = n_qp[k] = 1 for the absent directions and
+ *              forms the rows of the lower-dimensional problem, of length
+ *              #I_i1 #I_i2 (d = 2) or #I_i1 (d = 1), with the same calls.
+ *              For d = 1 the stiffness matrix is that of (a u')' with
+ *              K = a / J, the mass matrix that of u with weight J.
  *   p          degree, WQ_MIN_P..WQ_MAX_P; the same in every direction.
  *   n_knots[d] length of each knot vector (n_l + p + 1).
  *   knots[d]   host pointers to FP64 knot vectors: open (first and last
@@ -141,7 +145,8 @@ wq_status wq_bind(wq_plan* plan, void* workspace, size_t bytes, hipStream_t stre
  *      map F(zeta) = sum_i C_i B_i(zeta), det J, and the coefficient field
  *      (det J; K = a det J J^{-1} J^{-T}) stored in the plan's precision.
  *   ctrl_dev  device FP64 control points, [n3][n2][n1][3] (i1 fastest,
- *             physical x,y,z innermost; [n2][n1][2] for d = 2); copied
+ *             physical x,y,z innermost; [n2][n1][2] for d = 2, [n1] for
+ *             d = 1, which must increase strictly so that J > 0); copied
  *             into the workspace, so the
  *             caller may free it after the call has completed on stream.
  *   coef_dev  device FP64 array of the diffusion coefficient a at the
@@ -165,7 +170,7 @@ wq_status wq_setup(wq_plan* plan, const double* ctrl_dev, const double* coef_dev
 wq_status wq_set_coefficient(wq_plan* plan, const double* coef_dev, hipStream_t stream);
 
 /* Physical quadrature points F(x_q) into x_dev[n_qp3][n_qp2][n_qp1][3]
- * (x_dev[n_qp2][n_qp1][2] for d = 2; device FP64), e.g. to sample a
+ * (x_dev[n_qp2][n_qp1][2] for d = 2, [n_qp1] for d = 1; device FP64), e.g. to sample a
  * coefficient a(x).  Requires wq_setup. */
 wq_status wq_qp_physical(const wq_plan* plan, double* x_dev, hipStream_t stream);
 
@@ -275,7 +280,7 @@ void wq_batch_destroy(wq_batch* batch);
  * shares that GPU's array: calls that overlap on one GPU (different streams,
  * different plans) race and must be ordered by the caller.
  * Errors: as wq_assemble; WQ_ENOSPACE if one plane of the buffer,
- * n_qp1 * n_qp2 * (2p+1, or 1 for d = 2) * (8 channels with WQ_STIFF, else
+ * n_qp1 * n_qp2 * (2p+1, or 1 for d < 3) * (8 channels with WQ_STIFF, else
  * 1) * value size, exceeds the array.
  */
 #define WQ_STATIC_SCRATCH_BYTES ((size_t)64 << 20)

@@ -86,7 +86,9 @@ class Plan:
 
     def qp_physical(self, stream=None):
         import torch
-        shape = (self.n_qp[2], self.n_qp[1], self.n_qp[0], 3) if self.d == 3 else (self.n_qp[1], self.n_qp[0], 2)
+        shape = {3: (self.n_qp[2], self.n_qp[1], self.n_qp[0], 3),
+                 2: (self.n_qp[1], self.n_qp[0], 2),
+                 1: (self.n_qp[0], 1)}[self.d]
         x = torch.empty(shape, dtype=torch.float64, device="cuda")
         check(_wq.wq_qp_physical(self._h, _ptr(x), _stream(stream)), self._h)
         return x

@@ -591,8 +591,8 @@ hipError_t batch_launch(const BatchClassView& b, int first_blocks, int grid, hip
 template <int P, typename T>
 hipError_t batch_pt(const BatchClassView& b, int d, bool stiff, int first_blocks, int grid, hipStream_t s) {
   if (stiff)
-    return d == 2 ? batch_launch<P, T, true, true>(b, first_blocks, grid, s) : batch_launch<P, T, true, false>(b, first_blocks, grid, s);
-  return d == 2 ? batch_launch<P, T, false, true>(b, first_blocks, grid, s) : batch_launch<P, T, false, false>(b, first_blocks, grid, s);
+    return d <= 2 ? batch_launch<P, T, true, true>(b, first_blocks, grid, s) : batch_launch<P, T, true, false>(b, first_blocks, grid, s);
+  return d <= 2 ? batch_launch<P, T, false, true>(b, first_blocks, grid, s) : batch_launch<P, T, false, false>(b, first_blocks, grid, s);
 }
 
 template <int P>
@@ -606,11 +606,11 @@ constexpr int parts_of() { return Shape<P, T, STIFF, PLANE>::NPART; }
 template <int P>
 int parts_p(int d, int prec, bool stiff) {
   if (prec == WQ_FP64) {
-    if (stiff) return d == 2 ? parts_of<P, double, true, true>() : parts_of<P, double, true, false>();
-    return d == 2 ? parts_of<P, double, false, true>() : parts_of<P, double, false, false>();
+    if (stiff) return d <= 2 ? parts_of<P, double, true, true>() : parts_of<P, double, true, false>();
+    return d <= 2 ? parts_of<P, double, false, true>() : parts_of<P, double, false, false>();
   }
-  if (stiff) return d == 2 ? parts_of<P, float, true, true>() : parts_of<P, float, true, false>();
-  return d == 2 ? parts_of<P, float, false, true>() : parts_of<P, float, false, false>();
+  if (stiff) return d <= 2 ? parts_of<P, float, true, true>() : parts_of<P, float, true, false>();
+  return d <= 2 ? parts_of<P, float, false, true>() : parts_of<P, float, false, false>();
 }
 
 // The rows of the pencils with i3 in [i3a, i3b): k_first fills the Y planes
@@ -641,12 +641,12 @@ hipError_t push_launch(const PlanView& v, void* out, hipStream_t s, int i3a, int
 template <int P, typename T>
 hipError_t assemble_pt(const PlanView& v, int which, void* mass, void* stiff, hipStream_t s, int i3a, int i3b) {
   if (which & WQ_MASS) {
-    hipError_t e = v.d == 2 ? push_launch<P, T, false, true>(v, mass, s, i3a, i3b)
+    hipError_t e = v.d <= 2 ? push_launch<P, T, false, true>(v, mass, s, i3a, i3b)
                             : push_launch<P, T, false, false>(v, mass, s, i3a, i3b);
     if (e != hipSuccess) return e;
   }
   if (which & WQ_STIFF) {
-    hipError_t e = v.d == 2 ? push_launch<P, T, true, true>(v, stiff, s, i3a, i3b)
+    hipError_t e = v.d <= 2 ? push_launch<P, T, true, true>(v, stiff, s, i3a, i3b)
                             : push_launch<P, T, true, false>(v, stiff, s, i3a, i3b);
     if (e != hipSuccess) return e;
   }
@@ -735,7 +735,7 @@ int push_parts(int p, int d, int prec, bool stiff) {
 
 size_t static_plane_bytes(const PlanView& v, int which) {
   const size_t elem = v.prec == WQ_FP64 ? 8 : 4;
-  const size_t icy = v.d == 2 ? 1 : size_t(icap_of(v.p));
+  const size_t icy = v.d <= 2 ? 1 : size_t(icap_of(v.p));
   const size_t nch = (which & WQ_STIFF) ? size_t(kYChannels) : 1;
   return size_t(v.dir[0].nq) * size_t(v.dir[1].nq) * icy * nch * elem;
 }

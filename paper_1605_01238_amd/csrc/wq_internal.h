@@ -49,6 +49,11 @@ __host__ __device__ inline int span_last_q(int e, int p, int nel) {
 }
 // Q_i = [qs, qs + qc)
 __host__ __device__ inline void q_range(int i, int p, int nel, int& qs, int& qc) {
+  if (nel == 0) {   // trivial direction of a 1D or 2D problem: one point
+    qs = 0;
+    qc = 1;
+    return;
+  }
   int e0 = i - p > 0 ? i - p : 0;
   int e1 = i + 1 < nel ? i + 1 : nel;
   qs = span_first_q(e0, p, nel);
@@ -91,8 +96,9 @@ struct DirView {
 struct PlanView {
   int p;
   int prec;
-  int d;                 // 3, or 2: then direction 3 is the trivial one (one
-                         // function, one point, nel = 0, operator T^(0,0) = 1)
+  int d;                 // 3, 2 or 1: directions d+1..3 are trivial (one
+                         // function, one point, nel = 0, rule w^(0,0) = 1,
+                         // B^(0) = 1, every other rule and B^(1) zero)
   DirView dir[3];
   void* field;           // kNumChannels * nqtot in the plan precision
   void* ybuf;            // [n3][nq2][nq1][icap][kYChannels]: field contracted over q3 per test index i3

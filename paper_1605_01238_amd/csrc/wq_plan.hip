@@ -144,7 +144,7 @@ wq_status wq_plan_create(int d, int p, const int64_t* n_knots, const double* con
                          int precision, wq_plan** out) {
   if (!out) return create_fail(WQ_EINVAL, "null output pointer");
   *out = nullptr;
-  if (d != 2 && d != 3) return create_fail(WQ_EINVAL, "d must be 2 or 3");
+  if (d < 1 || d > 3) return create_fail(WQ_EINVAL, "d must be 1, 2 or 3");
   if (p < WQ_MIN_P || p > WQ_MAX_P) return create_fail(WQ_EINVAL, "degree outside the compiled range");
   if (!n_knots || !knots) return create_fail(WQ_EINVAL, "null knot arrays");
   if (precision != WQ_FP64 && precision != WQ_FP32) return create_fail(WQ_EINVAL, "precision must be WQ_FP64 or WQ_FP32");
@@ -154,8 +154,9 @@ wq_status wq_plan_create(int d, int p, const int64_t* n_knots, const double* con
   pl->p = p;
   pl->prec = precision;
   int64_t nrows = 1, nnz = 1, nqtot = 1;
-  // 2D: direction 3 is trivial (one function, one point; its tables are
-  // constant and written by wq_bind), so the 3D kernels form the 2D rows
+  // d < 3: directions d+1..3 are trivial (one function, one point; their
+  // tables are constant and written by wq_bind), so the 3D kernels form the
+  // rows of the lower-dimensional problem
   for (int k = d; k < 3; ++k) {
     pl->nel[k] = 0;
     pl->n[k] = 1;
@@ -248,16 +249,25 @@ wq_status wq_bind(wq_plan* plan, void* workspace, size_t bytes, hipStream_t stre
                                   plan->knots[k].size() * 8, hipMemcpyHostToDevice, stream);
     if (e != hipSuccess) return hip_fail(plan, e, "wq_bind: knot upload");
   }
-  if (plan->d == 2) {   // the trivial direction: qspan = 0, T^(0,0) = 1, other rules 0
+  // the trivial directions: qspan = 0, T^(0,0) = B^(0) = w^(0,0) = 1 at the
+  // one point and function, every other rule and B^(1) zero
+  for (int k = plan->d; k < 3; ++k) {
     const int ic = wq::icap_of(plan->p), qc = wq::qcap_of(plan->p);
     static const double one64 = 1.0;
     static const float one32 = 1.0f;
     const wq::Layout& L = plan->lay;
-    hipError_t e = hipMemsetAsync(plan->ws + L.qspan[2], 0, 4, stream);
-    if (e == hipSuccess) e = hipMemsetAsync(plan->ws + L.op64[2], 0, size_t(4) * ic * qc * 8, stream);
-    if (e == hipSuccess) e = hipMemsetAsync(plan->ws + L.op32[2], 0, size_t(4) * ic * qc * 4, stream);
-    if (e == hipSuccess) e = hipMemcpyAsync(plan->ws + L.op64[2], &one64, 8, hipMemcpyHostToDevice, stream);
-    if (e == hipSuccess) e = hipMemcpyAsync(plan->ws + L.op32[2], &one32, 4, hipMemcpyHostToDevice, stream);
+    char* w = plan->ws;
+    hipError_t e = hipMemsetAsync(w + L.qspan[k], 0, 4, stream);
+    if (e == hipSuccess) e = hipMemsetAsync(w + L.op64[k], 0, size_t(4) * ic * qc * 8, stream);
+    if (e == hipSuccess) e = hipMemsetAsync(w + L.op32[k], 0, size_t(4) * ic * qc * 4, stream);
+    if (e == hipSuccess) e = hipMemsetAsync(w + L.bt64[k], 0, size_t(2) * ic * qc * 8, stream);
+    if (e == hipSuccess) e = hipMemsetAsync(w + L.bt32[k], 0, size_t(2) * ic * qc * 4, stream);
+    if (e == hipSuccess) e = hipMemsetAsync(w + L.wt64[k], 0, size_t(4) * qc * 8, stream);
+    if (e == hipSuccess) e = hipMemsetAsync(w + L.wt32[k], 0, size_t(4) * qc * 4, stream);
+    for (size_t off : {L.op64[k], L.bt64[k], L.wt64[k]})
+      if (e == hipSuccess) e = hipMemcpyAsync(w + off, &one64, 8, hipMemcpyHostToDevice, stream);
+    for (size_t off : {L.op32[k], L.bt32[k], L.wt32[k]})
+      if (e == hipSuccess) e = hipMemcpyAsync(w + off, &one32, 4, hipMemcpyHostToDevice, stream);
     if (e != hipSuccess) return hip_fail(plan, e, "wq_bind: trivial direction");
   }
   hipError_t e = hipMemsetAsync(plan->ws + plan->lay.flags, 0, wq::kNumFlags * 4, stream);
@@ -303,8 +313,8 @@ wq_status wq_setup(wq_plan* plan, const double* ctrl_dev, const double* coef_dev
   plan->rules_launched = true;
   if (plan->d == 3) {
     e = wq::launch_ctrl_diff(v, ctrl_dev, stream);
-  } else {   // the 2D geometry reads the plan's copy of the net directly
-    e = hipMemcpyAsync(v.ctrl, ctrl_dev, size_t(plan->nrows) * 2 * 8, hipMemcpyDeviceToDevice, stream);
+  } else {   // the 1D and 2D geometry kernels read the plan's copy of the net directly
+    e = hipMemcpyAsync(v.ctrl, ctrl_dev, size_t(plan->nrows) * plan->d * 8, hipMemcpyDeviceToDevice, stream);
   }
   if (e != hipSuccess) return hip_fail(plan, e, "wq_setup: control-net differences");
   e = wq::launch_geometry(v, coef_dev, nullptr, stream);

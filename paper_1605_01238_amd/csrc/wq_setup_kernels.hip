@@ -87,7 +87,11 @@ __device__ inline double wave_sum(double x) {
 
 // ---------------------------------------------------------------------------
 // Quadrature points and the p+1 nonzero B-spline values/derivatives there
-// (FP64 tables for the geometry stage).
+// (FP64 tables for the geometry stage).  The tables are evaluated at the
+// point in double-double and then rounded, so that they belong to the same
+// point as the rules: a boundary point a + h (q+1)/(p+2) is not an FP64
+// number in general, and at |x| >> h its FP64 rounding moves it by a
+// fraction eps |x| / h of the span.
 template <int P>
 __global__ __launch_bounds__(256) void k_points(PlanView v) {
   const int dir = blockIdx.y;
@@ -96,11 +100,18 @@ __global__ __launch_bounds__(256) void k_points(PlanView v) {
   if (q >= d.nq) return;
   int e;
   const dd xd = qp_coord(d.knots, P, d.nel, q, e);
-  const double x = xd.hi;
-  double N[P + 1], D[P + 1], Nm[P], Dm[P];
-  basis_funs<P, double>(d.knots, e + P, x, N, D);
-  basis_funs<P - 1, double>(d.knots, e + P, x, Nm, Dm);   // degree p-1, functions e+1 .. e+p
-  d.x[q] = x;
+  dd Nx[P + 1], Dx[P + 1], Nmx[P], Dmx[P];
+  basis_funs<P, dd>(d.knots, e + P, xd, Nx, Dx);
+  basis_funs<P - 1, dd>(d.knots, e + P, xd, Nmx, Dmx);   // degree p-1, functions e+1 .. e+p
+  double N[P + 1], D[P + 1], Nm[P];
+#pragma unroll
+  for (int r = 0; r <= P; ++r) {
+    N[r] = Nx[r].hi;
+    D[r] = Dx[r].hi;
+  }
+#pragma unroll
+  for (int r = 0; r < P; ++r) Nm[r] = Nmx[r].hi;
+  d.x[q] = xd.hi;
   d.qspan[q] = e;
 #pragma unroll
   for (int r = 0; r <= P; ++r) {
@@ -827,6 +838,40 @@ __global__ __launch_bounds__(256) void k_geo2d(PlanView v, const double* __restr
   f[6 * N + q] = T(0);
 }
 
+// 1D geometry (d = 1): F = sum_i C_i B_i, J = dF/dzeta from the differenced
+// control points (as in the 2D and 3D passes), det J = J and K = a J^{-1}
+// (eq. coef_stiff in one direction), stored in the 3D channel order with
+// zeros in the channels of the absent directions.
+template <int P, typename T>
+__global__ __launch_bounds__(256) void k_geo1d(PlanView v, const double* __restrict__ coef,
+                                               double* __restrict__ xphys) {
+  const int64_t qq = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (qq >= v.nqtot) return;
+  const DirView d1 = v.dir[0];
+  const int q = int(qq), e = d1.qspan[q];
+  const double* C = v.ctrl;   // [n1]
+  double F = 0.0, J = 0.0;
+#pragma unroll
+  for (int l = 0; l <= P; ++l) {
+    F += C[e + l] * d1.bv[q * (P + 1) + l];
+    if (l) J += (C[e + l] - C[e + l - 1]) * d1.bw[q * P + l - 1];
+  }
+  if (xphys) {
+    xphys[q] = F;
+    return;
+  }
+  if (!(J > 0.0) || !isfinite(J)) {
+    atomicAdd(&v.flags[FLAG_DETJ_BAD], 1);
+    atomicMin(&v.flags[FLAG_DETJ_FIRST], q);
+  }
+  T* f = static_cast<T*>(v.field);
+  const int64_t N = v.nqtot;
+  f[0 * N + q] = T(J);
+  f[1 * N + q] = T((coef ? coef[q] : 1.0) / J);
+#pragma unroll
+  for (int c = 2; c < kNumChannels; ++c) f[c * N + q] = T(0);
+}
+
 template <int P>
 hipError_t points_p(const PlanView& v, hipStream_t s) {
   int maxq = 0;
@@ -847,6 +892,13 @@ hipError_t rules_p(const PlanView& v, hipStream_t s) {
 template <int P>
 hipError_t geometry_p(const PlanView& v, const double* coef, double* xphys, hipStream_t s) {
   const unsigned blocks = unsigned((v.nqtot + 255) / 256);
+  if (v.d == 1) {
+    if (v.prec == WQ_FP64)
+      hipLaunchKernelGGL((k_geo1d<P, double>), dim3(blocks), dim3(256), 0, s, v, coef, xphys);
+    else
+      hipLaunchKernelGGL((k_geo1d<P, float>), dim3(blocks), dim3(256), 0, s, v, coef, xphys);
+    return hipGetLastError();
+  }
   if (v.d == 2) {
     if (v.prec == WQ_FP64)
       hipLaunchKernelGGL((k_geo2d<P, double>), dim3(blocks), dim3(256), 0, s, v, coef, xphys);

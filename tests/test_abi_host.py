@@ -61,8 +61,26 @@ def test_sizes_2d(p, nel):
     assert _wq.wq_qpoints(h, 2, x.ctypes.data_as(C.POINTER(C.c_double))) == _wq.WQ_EINVAL
     _wq.wq_plan_destroy(h)
     good = open_uniform_knots(p, 8)
-    assert make([good], p, d=1)[0] == _wq.WQ_EINVAL
+    assert make([good], p, d=0)[0] == _wq.WQ_EINVAL
     assert make([good] * 4, p, d=4)[0] == _wq.WQ_EINVAL
+
+
+@pytest.mark.parametrize("p,nel", [(2, 5), (4, 33), (6, 1000)])
+def test_sizes_1d(p, nel):
+    """A curve plan: directions 2 and 3 are trivial; a row has #I_i1 entries
+    (Section 3 count in one direction)."""
+    from paper_1605_01238_amd import _wq
+    from workloads import open_uniform_knots
+    st, h = make([open_uniform_knots(p, nel)], p)
+    assert st == 0
+    s = _wq.wq_sizes_t()
+    assert _wq.wq_sizes(h, C.byref(s)) == 0
+    n = nel + p
+    assert tuple(s.n) == (n, 1, 1) and s.n_rows == n
+    assert tuple(s.n_qp) == (2 * nel + 2 * p - 1, 1, 1)
+    assert s.nnz == (2 * p + 1) * n - p * (p + 1)
+    assert s.nnz == sum(min(n - 1, i + p) - max(0, i - p) + 1 for i in range(n))
+    _wq.wq_plan_destroy(h)
 
 
 @pytest.mark.parametrize("p,nel", [(2, (8, 8, 8)), (4, (32, 32, 32)), (6, (64, 64, 64)), (3, (5, 7, 9))])
