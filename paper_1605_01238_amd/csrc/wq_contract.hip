@@ -72,7 +72,7 @@ WQ_PUSH_CFG(4, double, true, 2, 9, 3, 3)
 WQ_PUSH_CFG(5, double, false, 2, 11, 2, 0)
 WQ_PUSH_CFG(5, double, true, 2, 11, 2, 0)
 WQ_PUSH_CFG(6, double, false, 1, 4, 8, 0)
-WQ_PUSH_CFG(6, double, true, 4, 13, 3, 0)
+WQ_PUSH_CFG(6, double, true, 4, 13, 3, 2)
 WQ_PUSH_CFG(2, float, false, 1, 5, 8, 0)
 WQ_PUSH_CFG(2, float, true, 1, 5, 3, 0)
 WQ_PUSH_CFG(3, float, false, 1, 7, 8, 0)
@@ -104,6 +104,9 @@ struct Shape {
   static constexpr size_t HBUF = size_t(C) * NH * QC * J3;
   static constexpr size_t GBUF = size_t(C) * NG * IC * J3;
   static constexpr size_t STAGE = size_t(J3) * IC * IC;
+  // Banded phase B for rows away from the boundary spans (off where it
+  // makes a register-bounded configuration spill).
+  static constexpr bool BAND2 = Cfg::WPE < 3;
   // For the stiffness, whose H buffer is large, the row stage shares it: H
   // is dead from the end of phase B to the merge of the next chunk, which is
   // where rows are stored.
@@ -214,8 +217,9 @@ __device__ __forceinline__ void first_body(const PlanView& v, int bx, int by) {
   T acc[ICY * NCH];
 #pragma unroll
   for (int k = 0; k < ICY * NCH; ++k) acc[k] = T(0);
-#pragma unroll 2
-  for (int qq3 = 0; qq3 < qc3; ++qq3) {
+  // one quadrature point qq3: the products with the nonzero operator
+  // entries jj in [lo, hi]
+  auto point = [&](int qq3, int lo, int hi) {
     const T* fk = f + plane * qq3;
     const T* t = T3 + qq3 * IC * 4;   // uniform: scalar loads
     if constexpr (STIFF) {
@@ -223,6 +227,7 @@ __device__ __forceinline__ void first_body(const PlanView& v, int bx, int by) {
       const T k12 = fk[4 * N], k13 = fk[5 * N], k23 = fk[6 * N];
 #pragma unroll
       for (int jj = 0; jj < ICY; ++jj) {
+        if (jj < lo || jj > hi) continue;
         const T t0 = t[jj * 4 + R00], t1 = t[jj * 4 + R10], t2 = t[jj * 4 + R01], t3 = t[jj * 4 + R11];
         T* a = acc + jj * NCH;
         a[0] += t0 * k11;
@@ -237,8 +242,19 @@ __device__ __forceinline__ void first_body(const PlanView& v, int bx, int by) {
     } else {
       const T k0 = fk[0];
 #pragma unroll
-      for (int jj = 0; jj < ICY; ++jj) acc[jj] += t[jj * 4 + R00] * k0;
+      for (int jj = 0; jj < ICY; ++jj)
+        if (jj >= lo && jj <= hi) acc[jj] += t[jj * 4 + R00] * k0;
     }
+  };
+  if (!PLANE && i3 >= P + 1 && i3 <= d3.nel - 2) {
+    // row i3 away from the boundary spans: 2P+1 points alternating span
+    // midpoints and knots, the operator's nonzeros in a fixed band (the
+    // same products as below without the exact zeros)
+#pragma unroll
+    for (int qq3 = 0; qq3 < 2 * P + 1; ++qq3) point(qq3, (qq3 + 1) / 2, qq3 / 2 + P);
+  } else {
+#pragma unroll 2
+    for (int qq3 = 0; qq3 < qc3; ++qq3) point(qq3, 0, ICY - 1);
   }
   // the wave's records are contiguous in Y: pass them through LDS in rounds
   // of LPR records so that consecutive lanes store consecutive elements
@@ -284,6 +300,9 @@ __device__ __forceinline__ void push_body(const PlanView& v, T* __restrict__ out
 
   int qs2, qc2, is2, ic2, is3, ic3;
   q_range(i2, P, d2.nel, qs2, qc2);
+  // rows whose support spans are all interior: Q_i2 and I_i2 in the fixed
+  // layout (2P+1 points from the midpoint of span i2-P, I_i2 from i2-P)
+  const bool band2 = S::BAND2 && i2 >= P + 1 && i2 <= d2.nel - 2;
   i_range(i2, P, n2, is2, ic2);
   i_range(i3, P, d3.n, is3, ic3);
   const int j3lo = part * J3;
@@ -324,14 +343,14 @@ __device__ __forceinline__ void push_body(const PlanView& v, T* __restrict__ out
       const int dlo = i1 < P ? P - i1 : 0;
       const int dhi = min(2 * P, P + n1 - 1 - i1);
       const int ic1 = dhi - dlo + 1;
+      const int seglen = ic1 * ic2;
+      T* o = out + pencil_start + row_mult * d1.prefix[i1] + int64_t(j3lo) * seglen;
       if (cl) {
 #pragma unroll
         for (int d = 0; d <= 2 * P; ++d)
           if (d >= dlo && d <= dhi) stage[(cu3 * ic2 + cj2) * ic1 + (d - dlo)] = acc[0][d];
       }
       __syncthreads();
-      const int seglen = ic1 * ic2;
-      T* o = out + pencil_start + row_mult * d1.prefix[i1] + int64_t(j3lo) * seglen;
       const int len = nj3 * seglen;
       for (int t = tid; t < len; t += NT) o[t] = stage[t];
       __syncthreads();
@@ -430,15 +449,34 @@ __device__ __forceinline__ void push_body(const PlanView& v, T* __restrict__ out
       for (int jj2 = 0; jj2 < IC; ++jj2) G[jj2] = T(0);
       const T* hb0 = hbuf + (size_t(c) * NH + h0) * QC * J3 + u;
       const T* hb1 = h1 >= 0 ? hbuf + (size_t(c) * NH + h1) * QC * J3 + u : hzero + u;
-#pragma unroll 2
-      for (int qq2 = 0; qq2 < qc2; ++qq2) {   // uniform trip count
-        const T x0 = hb0[qq2 * J3];
-        const T x1 = STIFF ? hb1[qq2 * J3] : T(0);
-        const T* b = B2 + __builtin_amdgcn_readfirstlane(qq2 * IC * 2);
+      if (band2) {
+        // row i2 away from the boundary spans: its 2P+1 points alternate
+        // span midpoints (P+1 nonzero functions) and knots (P), so the
+        // nonzero part of B2 is a fixed band; the zeros are skipped
 #pragma unroll
-        for (int jj2 = 0; jj2 < IC; ++jj2) {
-          if constexpr (STIFF) G[jj2] = fma(b[jj2 * 2 + 1], x1, fma(b[jj2 * 2], x0, G[jj2]));
-          else G[jj2] = fma(b[jj2 * 2], x0, G[jj2]);
+        for (int qq2 = 0; qq2 < 2 * P + 1; ++qq2) {
+          const T x0 = hb0[qq2 * J3];
+          const T x1 = STIFF ? hb1[qq2 * J3] : T(0);
+          const T* b = B2 + qq2 * IC * 2;
+          const int lo = (qq2 + 1) / 2, hi = qq2 / 2 + P;
+#pragma unroll
+          for (int jj2 = 0; jj2 < IC; ++jj2) {
+            if (jj2 < lo || jj2 > hi) continue;
+            if constexpr (STIFF) G[jj2] = fma(b[jj2 * 2 + 1], x1, fma(b[jj2 * 2], x0, G[jj2]));
+            else G[jj2] = fma(b[jj2 * 2], x0, G[jj2]);
+          }
+        }
+      } else {
+#pragma unroll 2
+        for (int qq2 = 0; qq2 < qc2; ++qq2) {   // uniform trip count
+          const T x0 = hb0[qq2 * J3];
+          const T x1 = STIFF ? hb1[qq2 * J3] : T(0);
+          const T* b = B2 + __builtin_amdgcn_readfirstlane(qq2 * IC * 2);
+#pragma unroll
+          for (int jj2 = 0; jj2 < IC; ++jj2) {
+            if constexpr (STIFF) G[jj2] = fma(b[jj2 * 2 + 1], x1, fma(b[jj2 * 2], x0, G[jj2]));
+            else G[jj2] = fma(b[jj2 * 2], x0, G[jj2]);
+          }
         }
       }
       T* gb = gbuf + (size_t(c * NG + g) * IC) * J3 + u;
@@ -567,11 +605,6 @@ template <int P, typename T, bool STIFF, bool PLANE>
 __global__ __launch_bounds__((Shape<P, T, STIFF, PLANE>::NT)) void k_push_batch(BatchClassView b) {
   push_batch_body<P, T, STIFF, PLANE>(b);
 }
-template <int P, typename T, bool STIFF>
-__global__ __launch_bounds__((Shape<P, T, STIFF>::NT))
-__attribute__((amdgpu_waves_per_eu(PushCfg<P, T, STIFF>::WPE))) void k_push_batch_wpe(BatchClassView b) {
-  push_batch_body<P, T, STIFF, false>(b);
-}
 
 __global__ void k_zero_counters(int* c, int n) {
   if (int(threadIdx.x) < n) c[threadIdx.x] = 0;
@@ -581,10 +614,9 @@ template <int P, typename T, bool STIFF, bool PLANE>
 hipError_t batch_launch(const BatchClassView& b, int first_blocks, int grid, hipStream_t s) {
   if (first_blocks > 0)
     hipLaunchKernelGGL((k_first_batch<P, T, STIFF, PLANE>), dim3(unsigned(first_blocks)), dim3(256), 0, s, b);
-  if constexpr (PushCfg<P, T, STIFF, PLANE>::WPE > 0)
-    hipLaunchKernelGGL((k_push_batch_wpe<P, T, STIFF>), dim3(unsigned(grid)), dim3(Shape<P, T, STIFF, PLANE>::NT), 0, s, b);
-  else
-    hipLaunchKernelGGL((k_push_batch<P, T, STIFF, PLANE>), dim3(unsigned(grid)), dim3(Shape<P, T, STIFF, PLANE>::NT), 0, s, b);
+  // (the persistent loop needs more registers than one pencil: the bounds
+  // of the single-patch configurations would make it spill)
+  hipLaunchKernelGGL((k_push_batch<P, T, STIFF, PLANE>), dim3(unsigned(grid)), dim3(Shape<P, T, STIFF, PLANE>::NT), 0, s, b);
   return hipGetLastError();
 }
 
