@@ -53,3 +53,41 @@ def compare_rows(problem, rows, rp, vals_flat, which):
         max_abs_d = max(max_abs_d, d)
         max_abs = max(max_abs, s)
     return row_err, max_abs_d / max_abs, worst
+
+
+# ---- oracle rows in parallel (spawned CPU workers; the oracle only) -------
+
+_WORKER = {}
+
+
+def _worker_init(knots, p, ctrl, coef):
+    from oracle.assembly import Problem
+    _WORKER["P"] = Problem(knots, p, ctrl, coef=coef)
+
+
+def _worker_rows(args):
+    rows, whichs = args
+    P = _WORKER["P"]
+    return [(int(r), w, P.row(int(r), w)) for r in rows for w in whichs]
+
+
+def oracle_rows_parallel(knots, p, ctrl, coef, rows, whichs, nproc=None):
+    """Oracle rows {(which, row): values} computed by `nproc` spawned worker
+    processes (each builds its own Problem; nothing there touches the GPU)."""
+    import multiprocessing as mp
+    import os
+    import time
+    nproc = nproc or max(1, min(16, os.cpu_count() or 1))
+    rows = [int(r) for r in rows]
+    chunks = [(rows[k::nproc * 4], tuple(whichs)) for k in range(nproc * 4)]
+    chunks = [c for c in chunks if c[0]]
+    t0 = time.time()
+    out = {}
+    ctx = mp.get_context("spawn")
+    with ctx.Pool(nproc, initializer=_worker_init, initargs=(list(knots), p, ctrl, coef)) as pool:
+        for k, res in enumerate(pool.imap_unordered(_worker_rows, chunks)):
+            for r, w, v in res:
+                out[(w, r)] = v
+            if k % 8 == 0:
+                print(f"[oracle] {len(out)}/{len(rows) * len(whichs)} rows ({time.time() - t0:.0f} s)", flush=True)
+    return out

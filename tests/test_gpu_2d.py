@@ -4,7 +4,7 @@ or on sampled rows, FP32 bulk within the rounding model of the 3D tests."""
 import numpy as np
 import pytest
 
-from parity_helpers import compare_rows, gather_rows, gpu_pipeline
+from parity_helpers import compare_rows, gather_rows, gpu_pipeline, oracle_rows_parallel
 from workloads import coefficient_field, control_net, open_uniform_knots, random_open_knots
 
 pytestmark = pytest.mark.gpu
@@ -60,7 +60,8 @@ def test_2d_fp32_bulk(p):
 
 
 def test_2d_large_sampled_rows():
-    """p = 4 on 128 x 96 elements: sampled rows (interior and boundary)."""
+    """p = 4 on 128 x 96 elements: about 130 sampled rows (boundary layers of
+    both directions, corners and uniform rows)."""
     from oracle.assembly import Problem
     p, nel = 4, (128, 96)
     kn = [open_uniform_knots(p, e) for e in nel]
@@ -71,14 +72,24 @@ def test_2d_large_sampled_rows():
     n1, n2 = P.n
     rng = np.random.default_rng(5)
     picks = [(0, 0), (1, 0), (n1 - 1, n2 - 1), (p, 3), (n1 - 2, 1), (2, n2 - 3)]
-    picks += [(int(a), int(b)) for a, b in zip(rng.integers(0, n1, 10), rng.integers(0, n2, 10))]
+    # the boundary layers of both directions, then uniform rows
+    lay1 = [0, 1, p - 1, p, n1 - p - 1, n1 - 2, n1 - 1]
+    lay2 = [0, 1, p - 1, p, n2 - p - 1, n2 - 2, n2 - 1]
+    picks += [(int(rng.choice(lay1)), int(b)) for b in rng.integers(0, n2, 32)]
+    picks += [(int(a), int(rng.choice(lay2))) for a in rng.integers(0, n1, 32)]
+    picks += [(int(a), int(b)) for a, b in zip(rng.integers(0, n1, 64), rng.integers(0, n2, 64))]
     rows = np.array(sorted({i1 + n1 * i2 for i1, i2 in picks}))
+    ref = oracle_rows_parallel(kn, p, ctrl, cf, rows, ("mass", "stiff"))
     rp, _ = gather_rows(row_ptr, stiff, rows)
     for r in rows[:6]:
         assert np.array_equal(col_idx[int(rp[r]):int(rp[r + 1])].cpu().numpy(), P.row_columns(int(r)))
+
+    class _Cached:
+        def row(self, r, which):
+            return ref[(which, r)]
     for which, vals in (("mass", mass), ("stiff", stiff)):
         rp, v = gather_rows(row_ptr, vals, rows)
-        row_err, _, worst = compare_rows(P, rows, rp, v, which)
+        row_err, _, worst = compare_rows(_Cached(), rows, rp, v, which)
         print(f"[2d 128x96 p=4] {which}: row-normwise {row_err:.2e} (row {worst})", flush=True)
         assert row_err <= FP64_TOL
 

@@ -8,7 +8,7 @@ FP64 and FP32 bulk) and p = 6 on 64^3 elements with a twisted perturbed map
 import numpy as np
 import pytest
 
-from parity_helpers import compare_rows, gather_rows, gpu_pipeline
+from parity_helpers import compare_rows, gather_rows, gpu_pipeline, oracle_rows_parallel
 from workloads import LARGE_P6, MID_P4, sample_rows
 
 pytestmark = pytest.mark.gpu
@@ -63,12 +63,9 @@ def mid_oracle():
     from oracle.assembly import Problem
     w = MID_P4
     P = Problem(w.knots(), w.p, w.ctrl(), coef=w.coefficient())
-    rows = sample_rows(w.n_dof(), w.p, 160, 160, seed=21)
-    ref = {}
-    for k, r in enumerate(rows):
-        ref[int(r)] = P.row(int(r), "stiff")
-        if k % 64 == 0:
-            print(f"[oracle p4] row {k}/{len(rows)}", flush=True)
+    rows = sample_rows(w.n_dof(), w.p, 512, 512, seed=21)
+    got = oracle_rows_parallel(w.knots(), w.p, w.ctrl(), w.coefficient(), rows, ("stiff",))
+    ref = {r: got[("stiff", r)] for r in (int(x) for x in rows)}
     return w, P, rows, ref
 
 
@@ -110,13 +107,8 @@ def large_oracle():
     from oracle.assembly import Problem
     w = LARGE_P6
     P = Problem(w.knots(), w.p, w.ctrl(), coef=None)
-    rows = sample_rows(w.n_dof(), w.p, 48, 48, seed=22)
-    ref = {}
-    for k, r in enumerate(rows):
-        ref[("stiff", int(r))] = P.row(int(r), "stiff")
-        ref[("mass", int(r))] = P.row(int(r), "mass")
-        if k % 16 == 0:
-            print(f"[oracle p6] row {k}/{len(rows)}", flush=True)
+    rows = sample_rows(w.n_dof(), w.p, 512, 512, seed=22)
+    ref = oracle_rows_parallel(w.knots(), w.p, w.ctrl(), None, rows, ("stiff", "mass"))
     return w, P, rows, ref
 
 

@@ -4,7 +4,7 @@ S 1 = 0 on every row."""
 import numpy as np
 import pytest
 
-from parity_helpers import compare_rows, gather_rows, gpu_pipeline
+from parity_helpers import compare_rows, gather_rows, gpu_pipeline, oracle_rows_parallel
 from workloads import SWEEP, sample_rows
 
 pytestmark = pytest.mark.gpu
@@ -25,8 +25,9 @@ def test_sweep_stiffness_sampled_rows(w):
     import torch
     from oracle.assembly import Problem
     P = Problem(w.knots(), w.p, w.ctrl(), coef=w.coefficient())
-    rows = sample_rows(w.n_dof(), w.p, 8, 8, seed=40 + w.p)
-    ref = {int(r): P.row(int(r), "stiff") for r in rows}
+    rows = sample_rows(w.n_dof(), w.p, 64, 64, seed=40 + w.p)
+    got = oracle_rows_parallel(w.knots(), w.p, w.ctrl(), w.coefficient(), rows, ("stiff",))
+    ref = {int(r): got[("stiff", int(r))] for r in rows}
     print(f"[{w.name}] oracle rows ready", flush=True)
     plan, row_ptr, col_idx, _, stiff = gpu_pipeline(w.knots(), w.p, w.ctrl(), w.coefficient(), which=2)
     assert plan.nnz == w.exact_nnz()
