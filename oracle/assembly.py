@@ -27,6 +27,11 @@ The same definitions in d = 2 (two directions, d^2 = 4 stiffness terms) are
 taken when two knot vectors are given, and in d = 1 (one direction, one
 stiffness term with K = a / J: the problem of Section 7.1) when one is.
 
+NURBS (the generalisation Section 3 names, with the polynomial denominator
+in the factor c): a rational map (weights given) changes only J; with
+basis="nurbs" the mass of the rational functions R_i = w_i B_i / W is the
+B-spline row with c = det J / W^2, scaled by w_i w_j.
+
 Pins (tests/test_oracle_assembly.py): direct == sum-factorized (the identity
 between eq:massquadrature and eq:sumfactorization), affine exactness against
 a closed Kronecker formula of exact 1D integrals and against SGQ, S 1 = 0,
@@ -39,7 +44,7 @@ from typing import Callable, Optional, Sequence
 import numpy as np
 
 from .geometry import (coefficients_from_jacobian, coefficients_from_jacobian_1d, coefficients_from_jacobian_2d,
-                       map_and_jacobian, map_and_jacobian_1d, map_and_jacobian_2d)
+                       map_and_jacobian, map_and_jacobian_1d, map_and_jacobian_2d, rational_map_and_jacobian)
 from .rules import rules_for
 
 
@@ -53,7 +58,14 @@ class Problem:
     knots, degree, control net, coefficient."""
 
     def __init__(self, knots3: Sequence, p: int, ctrl: np.ndarray,
-                 coef: Optional[Callable[[np.ndarray], np.ndarray]] = None):
+                 coef: Optional[Callable[[np.ndarray], np.ndarray]] = None,
+                 weights: Optional[np.ndarray] = None, basis: str = "bspline"):
+        """weights: NURBS weights of the control points (shape of the net
+        without its last axis) for a rational map, else None.  basis:
+        "bspline" (test and trial functions B_i, on any map) or "nurbs" (the
+        rational functions R_i = w_i B_i / W of the same net, mass only:
+        m_ij = w_i w_j int B_i B_j det J / W^2, the denominator folded into
+        the factor c as Section 3 describes)."""
         d = len(knots3)
         if d not in (1, 2, 3):
             raise ValueError("1D, 2D or 3D problems only")
@@ -66,6 +78,12 @@ class Problem:
         if self.ctrl.shape != tuple(reversed(self.n)) + (d,):
             raise ValueError("control net shape must be (n_d, ..., n1, d)")
         self.coef = coef
+        self.weights = None if weights is None else np.asarray(weights, dtype=np.float64)
+        if self.weights is not None and self.weights.shape != self.ctrl.shape[:-1]:
+            raise ValueError("weights must have the shape of the control net without its last axis")
+        if basis not in ("bspline", "nurbs") or (basis == "nurbs" and self.weights is None):
+            raise ValueError("basis 'nurbs' needs weights")
+        self.basis = basis
         self.B = [(r.table64(0), r.table64(1)) for r in self.rules]
 
     # ---- indices ---------------------------------------------------------
@@ -115,6 +133,12 @@ class Problem:
     GRID_LIMIT = 100_000   # quadrature grids up to this size are evaluated once
 
     def _geometry(self, X):
+        """(F, J) at the grid X; for a rational map also W (else None)."""
+        if self.weights is not None:
+            return rational_map_and_jacobian(self.knots3, self.p, self.ctrl, self.weights, X)
+        return self._polynomial_geometry(X) + (None,)
+
+    def _polynomial_geometry(self, X):
         if self.d == 3:
             return map_and_jacobian(self.knots3, self.p, self.ctrl, X[0], X[1], X[2])
         if self.d == 2:
@@ -126,11 +150,13 @@ class Problem:
                 1: coefficients_from_jacobian_1d}[self.d](J, a)
 
     def _fields_on(self, X):
-        F, J = self._geometry(X)
+        F, J, W = self._geometry(X)
         F = F.astype(np.float64)
         d = self.d
         a = None if self.coef is None else self.coef(F.reshape(-1, d)).reshape(F.shape[:d])
         det, K = self._coefficients(J, a)
+        if self.basis == "nurbs":
+            det = det / (W * W)
         return det.astype(np.float64), K.astype(np.float64), F
 
     def row_fields(self, row: int):
@@ -161,6 +187,8 @@ class Problem:
         det, K, _ = self.row_fields(row)
         if which == "mass":
             terms = [((0,) * d, (0,) * d, det)]
+        elif which == "stiff" and self.basis == "nurbs":
+            raise NotImplementedError("stiffness with NURBS test and trial functions")
         elif which == "stiff":
             terms = []
             for l in range(d):          # test-function derivative direction
@@ -188,7 +216,11 @@ class Problem:
                 raise ValueError(method)
             out = v if out is None else out + v
         # [j1, ..., jd] -> increasing linear column order (j1 fastest)
-        return np.ascontiguousarray(out.transpose(tuple(reversed(range(d))))).ravel()
+        vals = np.ascontiguousarray(out.transpose(tuple(reversed(range(d))))).ravel()
+        if self.basis == "nurbs":   # R_i R_j = w_i w_j B_i B_j / W^2
+            w = self.weights.ravel()
+            vals = vals * w[row] * w[self.row_columns(row)]
+        return vals
 
     def assemble(self, which: str, method: str = "sumfact") -> np.ndarray:
         N = int(np.prod(self.n))
@@ -211,10 +243,14 @@ class Problem:
                 W.append(0.5 * (b - a) * gw)
             pts.append(np.concatenate(P))
             wts.append(np.concatenate(W))
-        F, J = self._geometry(pts)
+        F, J, W = self._geometry(pts)
         F = F.astype(np.float64)
         a = None if self.coef is None else self.coef(F.reshape(-1, d)).reshape(F.shape[:d])
         det, K = self._coefficients(J, a)
+        if self.basis == "nurbs":
+            if which != "mass":
+                raise NotImplementedError("stiffness with NURBS test and trial functions")
+            det = det / (W * W)
         det, K = det.astype(np.float64), K.astype(np.float64)
         if d == 3:
             Wq = wts[0][:, None, None] * wts[1][None, :, None] * wts[2][None, None, :]
@@ -243,7 +279,11 @@ class Problem:
             return T.reshape(N, -1)
         if which == "mass":
             P0 = phi((0,) * d)
-            return (P0 * (Wq * det).ravel()[None, :]) @ P0.T
+            M = (P0 * (Wq * det).ravel()[None, :]) @ P0.T
+            if self.basis == "nurbs":
+                w = self.weights.ravel()
+                M = M * w[:, None] * w[None, :]
+            return M
         G = [phi(tuple(int(k == dd) for k in range(d))) for dd in range(d)]
         S = np.zeros((N, N))
         for l in range(d):

@@ -23,6 +23,8 @@ follow the same definitions with (p+1)^2 functions per point and a 2x2 J;
 the 1D forms (``map_and_jacobian_1d``, ``coefficients_from_jacobian_1d``)
 with p+1 functions per point, J = dF/dzeta, det J = J and K = a / J (the
 one-direction case of eq. coef_stiff, as in the problem of Section 7.1).
+``rational_map_and_jacobian`` evaluates a NURBS map through its homogeneous
+net (the same sums, then the quotient rule).
 
 Pins (tests/test_oracle_geometry.py): Greville control points give the
 identity map (J = I, K = I); an affine control net gives J = A everywhere;
@@ -78,9 +80,10 @@ def local_basis(knots: Sequence, p: int, pts: Sequence):
 def map_and_jacobian(knots3, p: int, ctrl: np.ndarray, X1, X2, X3):
     """F and J = dF/dzeta on the tensor grid X1 x X2 x X3.
 
-    ctrl: (n3, n2, n1, 3) control points (linear index i1 + n1(i2 + n2 i3)).
-    Returns F with shape (len(X1), len(X2), len(X3), 3) and J with shape
-    (len(X1), len(X2), len(X3), 3, 3), J[..., a, b] = dF_a / dzeta_b, in
+    ctrl: (n3, n2, n1, k) control points (linear index i1 + n1(i2 + n2 i3)),
+    k = 3 (or 4 for a homogeneous net).  Returns F with shape
+    (len(X1), len(X2), len(X3), k) and J with shape
+    (len(X1), len(X2), len(X3), k, 3), J[..., a, b] = dF_a / dzeta_b, in
     longdouble."""
     ctrl = np.asarray(ctrl).astype(LD)
     f1, V1, D1 = local_basis(knots3[0], p, X1)
@@ -88,8 +91,9 @@ def map_and_jacobian(knots3, p: int, ctrl: np.ndarray, X1, X2, X3):
     f3, V3, D3 = local_basis(knots3[2], p, X3)
     r = np.arange(p + 1)
     n1, n2, n3 = len(X1), len(X2), len(X3)
-    F = np.zeros((n1, n2, n3, 3), dtype=LD)
-    J = np.zeros((n1, n2, n3, 3, 3), dtype=LD)
+    k = ctrl.shape[-1]   # components (3, or 4 for a homogeneous net)
+    F = np.zeros((n1, n2, n3, k), dtype=LD)
+    J = np.zeros((n1, n2, n3, k, 3), dtype=LD)
     # gather the local (p+1)^3 control blocks for every grid point
     i1 = (f1[:, None] + r[None, :])            # (n1, p+1)
     i2 = (f2[:, None] + r[None, :])
@@ -177,15 +181,16 @@ def coefficients_from_jacobian_2d(J: np.ndarray, a: Optional[np.ndarray] = None)
 def map_and_jacobian_1d(knots1, p: int, ctrl: np.ndarray, X1):
     """F and J = dF/dzeta of a univariate map at the points X1.
 
-    ctrl: (n1, 1) control points.  Returns F with shape (len(X1), 1) and J
-    with shape (len(X1), 1, 1), in longdouble."""
-    ctrl = np.asarray(ctrl).astype(LD)[:, 0]
+    ctrl: (n1, k) control points (k components, 1 for a curve in the line).
+    Returns F with shape (len(X1), k) and J with shape (len(X1), k, 1), in
+    longdouble."""
+    ctrl = np.asarray(ctrl).astype(LD)
     f1, V1, D1 = local_basis(knots1[0], p, X1)
     i1 = f1[:, None] + np.arange(p + 1)[None, :]
-    C = ctrl[i1]                                   # (n_pts, p+1)
-    F = (V1 * C).sum(axis=1)
-    J = (D1 * C).sum(axis=1)
-    return F[:, None], J[:, None, None]
+    C = ctrl[i1]                                   # (n_pts, p+1, k)
+    F = np.einsum("ar,ark->ak", V1, C)
+    J = np.einsum("ar,ark->ak", D1, C)
+    return F, J[:, :, None]
 
 
 def coefficients_from_jacobian_1d(J: np.ndarray, a: Optional[np.ndarray] = None):
@@ -196,3 +201,28 @@ def coefficients_from_jacobian_1d(J: np.ndarray, a: Optional[np.ndarray] = None)
     if a is not None:
         K = K * np.asarray(a)[..., None, None]
     return det, K
+
+
+def rational_map_and_jacobian(knots, p: int, ctrl: np.ndarray, weights: np.ndarray, X):
+    """A NURBS map F = sum_i w_i C_i B_i / W, W = sum_i w_i B_i (the rational
+    generalisation Section 3 allows through the factor c), on the tensor grid
+    of the points X (one array per direction, d = len(knots)).
+
+    The spline map of the homogeneous net (w C, w) gives N = sum w_i C_i B_i,
+    W and their derivatives; then F = N / W and, by the quotient rule,
+    J = (dN - F dW^T) / W.  Returns (F[..., d], J[..., d, d], W[...]) in
+    longdouble, indexed like the polynomial forms."""
+    d = len(knots)
+    C = np.asarray(ctrl).astype(LD)
+    w = np.asarray(weights).astype(LD)[..., None]
+    H = np.concatenate([C * w, w], axis=-1)        # homogeneous net
+    if d == 3:
+        Fh, Jh = map_and_jacobian(knots, p, H, X[0], X[1], X[2])
+    elif d == 2:
+        Fh, Jh = map_and_jacobian_2d(knots, p, H, X[0], X[1])
+    else:
+        Fh, Jh = map_and_jacobian_1d(knots, p, H, X[0])
+    N, W = Fh[..., :d], Fh[..., d]
+    F = N / W[..., None]
+    J = (Jh[..., :d, :] - F[..., :, None] * Jh[..., d, None, :]) / W[..., None, None]
+    return F, J, W
