@@ -162,6 +162,31 @@ wq_status wq_bind(wq_plan* plan, void* workspace, size_t bytes, hipStream_t stre
  */
 wq_status wq_setup(wq_plan* plan, const double* ctrl_dev, const double* coef_dev, hipStream_t stream);
 
+/*
+ * NURBS (Section 3: a rational denominator enters through the factor c).
+ * As wq_setup, for the rational map F = sum_i w_i C_i B_i / sum_i w_i B_i:
+ *   weights_dev  device FP64 weights of the control points, [n3][n2][n1]
+ *                (as ctrl_dev without its last axis), all > 0; copied into
+ *                the workspace.  W <= 0 or det J <= 0 at a point is latched
+ *                like a bad geometry (WQ_EGEOM at wq_sync).
+ *   basis        WQ_BASIS_BSPLINE: test and trial functions are the
+ *                B-splines (both matrices; only J is rational).
+ *                WQ_BASIS_NURBS: they are the rational functions
+ *                R_i = w_i B_i / W of the same net; the mass is formed with
+ *                c = det J / W^2 and every entry (i, j) is then scaled by
+ *                w_i w_j (one extra pass over the values).  The stiffness
+ *                of rational functions is not formed: assembly calls with
+ *                WQ_STIFF return WQ_EINVAL.
+ * wq_set_coefficient and wq_qp_physical keep the rational map; a later
+ * wq_setup returns the plan to a polynomial map.  Batches (wq_batch_create)
+ * refuse plans set up with WQ_BASIS_NURBS.
+ * Errors: as wq_setup; WQ_EINVAL for a null weights pointer or another basis.
+ */
+#define WQ_BASIS_BSPLINE 0
+#define WQ_BASIS_NURBS 1
+wq_status wq_setup_nurbs(wq_plan* plan, const double* ctrl_dev, const double* weights_dev, const double* coef_dev,
+                         int basis, hipStream_t stream);
+
 /* New diffusion coefficient a on the same geometry: recomputes the
  * coefficient field (the geometry stage of wq_setup; the univariate rules
  * are kept); coef_dev as in wq_setup.  Requires a prior wq_setup.  Ordered

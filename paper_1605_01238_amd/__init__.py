@@ -12,9 +12,11 @@ from typing import Optional, Sequence
 import numpy as np
 
 from . import _wq
-from ._wq import (WQ_FP32, WQ_FP64, WQ_MASS, WQ_STATIC_SCRATCH_BYTES, WQ_STIFF, WQError, check)
+from ._wq import (WQ_BASIS_BSPLINE, WQ_BASIS_NURBS, WQ_FP32, WQ_FP64, WQ_MASS, WQ_STATIC_SCRATCH_BYTES, WQ_STIFF,
+                  WQError, check)
 
-__all__ = ["Batch", "Plan", "WQError", "WQ_FP32", "WQ_FP64", "WQ_MASS", "WQ_STATIC_SCRATCH_BYTES", "WQ_STIFF"]
+__all__ = ["Batch", "Plan", "WQError", "WQ_BASIS_BSPLINE", "WQ_BASIS_NURBS", "WQ_FP32", "WQ_FP64", "WQ_MASS",
+           "WQ_STATIC_SCRATCH_BYTES", "WQ_STIFF"]
 
 
 def _ptr(t) -> Optional[int]:
@@ -78,6 +80,18 @@ class Plan:
         if coef is not None and coef.numel() != self.n_qp_total:
             raise ValueError(f"coefficient must hold {self.n_qp_total} values")
         check(_wq.wq_setup(self._h, _ptr(ctrl), _ptr(coef), _stream(stream)), self._h)
+
+    def setup_nurbs(self, ctrl, weights, coef=None, basis: int = 0, stream=None):
+        """wq_setup_nurbs: a rational map with the control points' weights
+        (device float64, n_rows values); basis WQ_BASIS_BSPLINE (0) or
+        WQ_BASIS_NURBS (1, mass only)."""
+        if ctrl.numel() != self.n_rows * self.d:
+            raise ValueError(f"control net must hold {self.n_rows} x {self.d} values")
+        if weights.numel() != self.n_rows:
+            raise ValueError(f"weights must hold {self.n_rows} values")
+        if coef is not None and coef.numel() != self.n_qp_total:
+            raise ValueError(f"coefficient must hold {self.n_qp_total} values")
+        check(_wq.wq_setup_nurbs(self._h, _ptr(ctrl), _ptr(weights), _ptr(coef), basis, _stream(stream)), self._h)
 
     def set_coefficient(self, coef, stream=None):
         if coef is not None and coef.numel() != self.n_qp_total:

@@ -17,6 +17,8 @@ WQ_MASS, WQ_STIFF = 1, 2
 WQ_FP64, WQ_FP32 = 0, 1
 WQ_MIN_P, WQ_MAX_P = 2, 6
 WQ_STATIC_SCRATCH_BYTES = 64 << 20   # static scratch of wq_assemble_static, per GPU
+WQ_BASIS_BSPLINE = 0
+WQ_BASIS_NURBS = 1
 
 STATUS_NAMES = {0: "WQ_OK", -1: "WQ_EINVAL", -2: "WQ_EKNOTS", -3: "WQ_ESINGULAR", -4: "WQ_EGEOM",
                 -5: "WQ_ENOSPACE", -6: "WQ_EDEVICE", -7: "WQ_ESTATE"}
@@ -37,6 +39,7 @@ SIGNATURES = [
     ("wq_qpoints", C.c_int, [_P, C.c_int, C.POINTER(C.c_double)]),
     ("wq_bind", C.c_int, [_P, _P, C.c_size_t, _P]),
     ("wq_setup", C.c_int, [_P, _P, _P, _P]),
+    ("wq_setup_nurbs", C.c_int, [_P, _P, _P, _P, C.c_int, _P]),
     ("wq_set_coefficient", C.c_int, [_P, _P, _P]),
     ("wq_qp_physical", C.c_int, [_P, _P, _P]),
     ("wq_pattern", C.c_int, [_P, _P, _P, _P]),

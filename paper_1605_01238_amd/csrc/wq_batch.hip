@@ -153,6 +153,8 @@ wq_status check_ready(wq_batch* b, int which) {
   if (which <= 0 || (which & ~(WQ_MASS | WQ_STIFF))) return bfail(b, WQ_EINVAL, "which must be WQ_MASS, WQ_STIFF or both");
   for (size_t k = 0; k < b->plans.size(); ++k) {
     if (!b->plans[k]->setup_done) return bfail(b, WQ_ESTATE, "patch " + std::to_string(k) + " has no wq_setup");
+    if (b->plans[k]->nurbs_basis)
+      return bfail(b, WQ_EINVAL, "patch " + std::to_string(k) + ": rational test/trial functions (WQ_BASIS_NURBS) are not batched");
     if ((which & WQ_MASS) && !b->mass[k]) return bfail(b, WQ_EINVAL, "patch " + std::to_string(k) + ": no mass output");
     if ((which & WQ_STIFF) && !b->stiff[k]) return bfail(b, WQ_EINVAL, "patch " + std::to_string(k) + ": no stiffness output");
   }

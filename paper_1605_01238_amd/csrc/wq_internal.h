@@ -107,6 +107,8 @@ struct PlanView {
   int32_t* flags;        // kNumFlags
   int64_t nqtot;
   int y_i3;              // ybuf holds the first-contraction planes i3 >= y_i3
+  const double* wts;     // NURBS weights of the net ([n3][n2][n1]), or null for a polynomial map
+  int nurbs_basis;       // 1: rational test/trial functions (mass factor det J / W^2)
 };
 
 // One class (degree p, dimension d, precision) of a batch of patches, in
@@ -128,7 +130,7 @@ struct BatchClassView {
 
 struct Layout {
   size_t knots[3], x[3], qspan[3], bv[3], bd[3], bw[3], w[3], op64[3], op32[3], bt64[3], bt32[3], wt64[3], wt32[3], prefix[3], colt64[3], colt32[3];
-  size_t field, ybuf, ctrl, dctrl, flags, total;
+  size_t field, ybuf, ctrl, dctrl, wts, flags, total;
 };
 
 }  // namespace wq
@@ -143,6 +145,8 @@ struct wq_plan {
   size_t ws_bytes = 0;
   bool bound = false, setup_done = false;
   bool unit_coef = false;   // the field holds the coefficients of a = 1 (requests scale it)
+  bool rational = false;    // NURBS map: weights in the workspace
+  bool nurbs_basis = false; // rational test/trial functions (mass only)
   std::string err;
   // The univariate stage runs on a second stream, forked from the caller's
   // stream at wq_setup and joined by the calls that read its tables.
@@ -163,6 +167,9 @@ hipError_t launch_geometry(const PlanView& v, const double* coef, double* xphys_
 hipError_t launch_pattern(const PlanView& v, int64_t* row_ptr, int32_t* col_idx, hipStream_t s);
 hipError_t launch_qranges(const PlanView& v, int dir, int32_t* q_start, int32_t* q_count, hipStream_t s);
 // field_out = the plan's field with channels K (1..6) multiplied by a(x_q).
+// Row i, column j of a mass matrix with rational test/trial functions:
+// value * w_i * w_j (rows in closed-form CSR order).
+hipError_t launch_nurbs_scale(const PlanView& v, void* vals, hipStream_t s);
 hipError_t launch_scale_field(const PlanView& v, const double* coef, void* field_out, hipStream_t s);
 hipError_t launch_assemble(const PlanView& v, int which, void* mass, void* stiff, hipStream_t s);
 // The same rows with the first-contraction buffer in the library's static

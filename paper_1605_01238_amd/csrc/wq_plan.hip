@@ -85,6 +85,7 @@ void compute_layout(wq_plan* pl) {
   L.ybuf = take(ybytes > gbytes ? ybytes : gbytes);
   L.ctrl = take(size_t(pl->nrows) * 3 * 8);
   L.dctrl = take(size_t(pl->nrows) * 9 * 8);
+  L.wts = take(size_t(pl->nrows) * 8);
   L.flags = take(wq::kNumFlags * 4);
   L.total = off;
 }
@@ -131,6 +132,8 @@ wq::PlanView wq_plan::view() const {
   v.ybuf = ws + lay.ybuf;
   v.ctrl = reinterpret_cast<double*>(ws + lay.ctrl);
   v.dctrl = reinterpret_cast<double*>(ws + lay.dctrl);
+  v.wts = rational ? reinterpret_cast<const double*>(ws + lay.wts) : nullptr;
+  v.nurbs_basis = nurbs_basis ? 1 : 0;
   v.flags = reinterpret_cast<int32_t*>(ws + lay.flags);
   v.nqtot = nqtot;
   return v;
@@ -297,10 +300,36 @@ static hipError_t join_rules(const wq_plan* plan, hipStream_t stream) {
   return plan->rules_launched ? hipStreamWaitEvent(stream, plan->ev_rules, 0) : hipSuccess;
 }
 
+static const char nurbs_stiff_msg[] =
+    "the stiffness of rational (NURBS) test and trial functions is not formed: set up with WQ_BASIS_BSPLINE";
+static wq_status setup_common(wq_plan* plan, const double* ctrl_dev, const double* coef_dev, hipStream_t stream);
+
 wq_status wq_setup(wq_plan* plan, const double* ctrl_dev, const double* coef_dev, hipStream_t stream) {
   if (!plan) return WQ_EINVAL;
   if (!plan->bound) return fail(plan, WQ_ESTATE, "wq_setup before wq_bind");
   if (!ctrl_dev) return fail(plan, WQ_EINVAL, "null control net");
+  plan->rational = false;
+  plan->nurbs_basis = false;
+  return setup_common(plan, ctrl_dev, coef_dev, stream);
+}
+
+wq_status wq_setup_nurbs(wq_plan* plan, const double* ctrl_dev, const double* weights_dev, const double* coef_dev,
+                         int basis, hipStream_t stream) {
+  if (!plan) return WQ_EINVAL;
+  if (!plan->bound) return fail(plan, WQ_ESTATE, "wq_setup_nurbs before wq_bind");
+  if (!ctrl_dev) return fail(plan, WQ_EINVAL, "null control net");
+  if (!weights_dev) return fail(plan, WQ_EINVAL, "null weights");
+  if (basis != WQ_BASIS_BSPLINE && basis != WQ_BASIS_NURBS)
+    return fail(plan, WQ_EINVAL, "basis must be WQ_BASIS_BSPLINE or WQ_BASIS_NURBS");
+  hipError_t e = hipMemcpyAsync(plan->ws + plan->lay.wts, weights_dev, size_t(plan->nrows) * 8,
+                                hipMemcpyDeviceToDevice, stream);
+  if (e != hipSuccess) return hip_fail(plan, e, "wq_setup_nurbs: weights copy");
+  plan->rational = true;
+  plan->nurbs_basis = basis == WQ_BASIS_NURBS;
+  return setup_common(plan, ctrl_dev, coef_dev, stream);
+}
+
+static wq_status setup_common(wq_plan* plan, const double* ctrl_dev, const double* coef_dev, hipStream_t stream) {
   wq::PlanView v = plan->view();
   hipError_t e;
   // univariate stage on the second stream, after everything already queued
@@ -360,6 +389,7 @@ wq_status wq_assemble_request(wq_plan* plan, void* ctx, size_t ctx_bytes, const 
   if ((which & WQ_STIFF) && !stiff) return fail(plan, WQ_EINVAL, "null stiffness output");
   if (!plan->setup_done) return fail(plan, WQ_ESTATE, "wq_assemble_request before wq_setup");
   if (!plan->unit_coef) return fail(plan, WQ_ESTATE, "wq_assemble_request needs the plan's field for a = 1 (set up or set with a NULL coefficient)");
+  if (plan->nurbs_basis && (which & WQ_STIFF)) return fail(plan, WQ_EINVAL, nurbs_stiff_msg);
   size_t f, y, total;
   request_layout(plan, &f, &y, &total);
   if (ctx_bytes < total) return fail(plan, WQ_ENOSPACE, "request context smaller than wq_request_bytes()");
@@ -373,6 +403,7 @@ wq_status wq_assemble_request(wq_plan* plan, void* ctx, size_t ctx_bytes, const 
   v.field = c + f;
   v.ybuf = c + y;
   e = wq::launch_assemble(v, which, mass, stiff, stream);
+  if (e == hipSuccess && plan->nurbs_basis) e = wq::launch_nurbs_scale(v, mass, stream);
   if (e != hipSuccess) return hip_fail(plan, e, "wq_assemble_request: contraction kernel");
   return WQ_OK;
 }
@@ -397,9 +428,11 @@ wq_status wq_assemble(wq_plan* plan, int which, void* mass, void* stiff, hipStre
   if ((which & WQ_MASS) && !mass) return fail(plan, WQ_EINVAL, "null mass output");
   if ((which & WQ_STIFF) && !stiff) return fail(plan, WQ_EINVAL, "null stiffness output");
   if (!plan->setup_done) return fail(plan, WQ_ESTATE, "wq_assemble before wq_setup");
+  if (plan->nurbs_basis && (which & WQ_STIFF)) return fail(plan, WQ_EINVAL, nurbs_stiff_msg);
   hipError_t e = join_rules(plan, stream);
   if (e != hipSuccess) return hip_fail(plan, e, "wq_assemble: join");
   e = wq::launch_assemble(plan->view(), which, mass, stiff, stream);
+  if (e == hipSuccess && plan->nurbs_basis) e = wq::launch_nurbs_scale(plan->view(), mass, stream);
   if (e != hipSuccess) return hip_fail(plan, e, "wq_assemble: contraction kernel");
   return WQ_OK;
 }
@@ -410,6 +443,7 @@ wq_status wq_assemble_static(wq_plan* plan, int which, void* mass, void* stiff, 
   if ((which & WQ_MASS) && !mass) return fail(plan, WQ_EINVAL, "null mass output");
   if ((which & WQ_STIFF) && !stiff) return fail(plan, WQ_EINVAL, "null stiffness output");
   if (!plan->setup_done) return fail(plan, WQ_ESTATE, "wq_assemble_static before wq_setup");
+  if (plan->nurbs_basis && (which & WQ_STIFF)) return fail(plan, WQ_EINVAL, nurbs_stiff_msg);
   const wq::PlanView v = plan->view();
   const size_t pb = wq::static_plane_bytes(v, which);
   if (pb > wq::kStaticScratchBytes) {
@@ -421,6 +455,7 @@ wq_status wq_assemble_static(wq_plan* plan, int which, void* mass, void* stiff, 
   hipError_t e = join_rules(plan, stream);
   if (e != hipSuccess) return hip_fail(plan, e, "wq_assemble_static: join");
   e = wq::launch_assemble_static(v, which, mass, stiff, stream);
+  if (e == hipSuccess && plan->nurbs_basis) e = wq::launch_nurbs_scale(v, mass, stream);
   if (e != hipSuccess) return hip_fail(plan, e, "wq_assemble_static");
   return WQ_OK;
 }

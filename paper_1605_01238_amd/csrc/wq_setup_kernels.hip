@@ -872,6 +872,137 @@ __global__ __launch_bounds__(256) void k_geo1d(PlanView v, const double* __restr
   for (int c = 2; c < kNumChannels; ++c) f[c * N + q] = T(0);
 }
 
+// NURBS maps (Section 3 lets rational functions enter through the factor
+// c): F = N / W with N = sum_i w_i C_i B_i and W = sum_i w_i B_i over the
+// (p+1)^d functions nonzero at the point, their derivatives from the
+// differenced homogeneous net (w_i C_i, w_i) as for the polynomial maps, and
+// J = (dN - F dW^T) / W by the quotient rule.  The field then as for a
+// polynomial map; with rational test and trial functions the mass factor is
+// det J / W^2 (the values are scaled by w_i w_j after the contraction).
+// One thread per point, direct sums: a set-up kernel.
+template <int P, typename T, int D>
+__global__ __launch_bounds__(256) void k_geo_rational(PlanView v, const double* __restrict__ coef,
+                                                      double* __restrict__ xphys) {
+  const int64_t q = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (q >= v.nqtot) return;
+  const DirView d1 = v.dir[0], d2 = v.dir[1], d3 = v.dir[2];
+  const int nq1 = d1.nq, nq2 = d2.nq, n1 = d1.n, n2 = d2.n;
+  const int q1 = int(q % nq1), q2 = int((q / nq1) % nq2), q3 = int(q / (int64_t(nq1) * nq2));
+  constexpr int L2 = D >= 2 ? P : 0, L3 = D == 3 ? P : 0;
+  const int e1 = d1.qspan[q1], e2 = D >= 2 ? d2.qspan[q2] : 0, e3 = D == 3 ? d3.qspan[q3] : 0;
+  double v1[P + 1], g1[P + 1], v2[P + 1], g2[P + 1], v3[P + 1], g3[P + 1];
+#pragma unroll
+  for (int l = 0; l <= P; ++l) {
+    v1[l] = d1.bv[q1 * (P + 1) + l];
+    g1[l] = l ? d1.bw[q1 * P + l - 1] : 0.0;
+    v2[l] = D >= 2 ? d2.bv[q2 * (P + 1) + l] : 1.0;
+    g2[l] = (D >= 2 && l) ? d2.bw[q2 * P + l - 1] : 0.0;
+    v3[l] = D == 3 ? d3.bv[q3 * (P + 1) + l] : 1.0;
+    g3[l] = (D == 3 && l) ? d3.bw[q3 * P + l - 1] : 0.0;
+  }
+  // homogeneous control point (w C, w) of net index idx
+  auto hom = [&](int64_t idx, double (&h)[D + 1]) {
+    const double w = v.wts[idx];
+#pragma unroll
+    for (int a = 0; a < D; ++a) h[a] = w * v.ctrl[idx * D + a];
+    h[D] = w;
+  };
+  double Nv[D + 1] = {}, dN[D + 1][D] = {};
+  for (int l3 = 0; l3 <= L3; ++l3) {
+    for (int l2 = 0; l2 <= L2; ++l2) {
+#pragma unroll
+      for (int l1 = 0; l1 <= P; ++l1) {
+        const int64_t idx = (int64_t(e3 + l3) * n2 + (e2 + l2)) * n1 + (e1 + l1);
+        double h[D + 1], hm[D + 1];
+        hom(idx, h);
+        const double b = v1[l1] * v2[l2] * v3[l3];
+#pragma unroll
+        for (int a = 0; a <= D; ++a) Nv[a] += h[a] * b;
+        if (l1) {
+          hom(idx - 1, hm);
+          const double g = g1[l1] * v2[l2] * v3[l3];
+#pragma unroll
+          for (int a = 0; a <= D; ++a) dN[a][0] += (h[a] - hm[a]) * g;
+        }
+        if (D >= 2 && l2) {
+          hom(idx - n1, hm);
+          const double g = v1[l1] * g2[l2] * v3[l3];
+#pragma unroll
+          for (int a = 0; a <= D; ++a) dN[a][D >= 2 ? 1 : 0] += (h[a] - hm[a]) * g;
+        }
+        if (D == 3 && l3) {
+          hom(idx - int64_t(n1) * n2, hm);
+          const double g = v1[l1] * v2[l2] * g3[l3];
+#pragma unroll
+          for (int a = 0; a <= D; ++a) dN[a][D - 1] += (h[a] - hm[a]) * g;
+        }
+      }
+    }
+  }
+  const double W = Nv[D];
+  double F[D], J[3][3] = {{1, 0, 0}, {0, 1, 0}, {0, 0, 1}};
+#pragma unroll
+  for (int a = 0; a < D; ++a) F[a] = Nv[a] / W;
+  if (xphys) {
+#pragma unroll
+    for (int a = 0; a < D; ++a) xphys[q * D + a] = F[a];
+    return;
+  }
+#pragma unroll
+  for (int a = 0; a < D; ++a)
+#pragma unroll
+    for (int b = 0; b < D; ++b) J[a][b] = (dN[a][b] - F[a] * dN[D][b]) / W;
+  // cofactors of J (the absent directions are the identity)
+  const double c00 = J[1][1] * J[2][2] - J[1][2] * J[2][1];
+  const double c01 = J[1][2] * J[2][0] - J[1][0] * J[2][2];
+  const double c02 = J[1][0] * J[2][1] - J[1][1] * J[2][0];
+  const double c10 = J[0][2] * J[2][1] - J[0][1] * J[2][2];
+  const double c11 = J[0][0] * J[2][2] - J[0][2] * J[2][0];
+  const double c12 = J[0][1] * J[2][0] - J[0][0] * J[2][1];
+  const double c20 = J[0][1] * J[1][2] - J[0][2] * J[1][1];
+  const double c21 = J[0][2] * J[1][0] - J[0][0] * J[1][2];
+  const double c22 = J[0][0] * J[1][1] - J[0][1] * J[1][0];
+  const double det = J[0][0] * c00 + J[0][1] * c01 + J[0][2] * c02;
+  if (!(det > 0.0) || !(W > 0.0) || !isfinite(det)) {
+    atomicAdd(&v.flags[FLAG_DETJ_BAD], 1);
+    atomicMin(&v.flags[FLAG_DETJ_FIRST], int(q));
+  }
+  const double s = (coef ? coef[q] : 1.0) / det;
+  T* f = static_cast<T*>(v.field);
+  const int64_t N = v.nqtot;
+  f[0 * N + q] = T(v.nurbs_basis ? det / (W * W) : det);
+  f[1 * N + q] = T(s * (c00 * c00 + c10 * c10 + c20 * c20));
+  f[2 * N + q] = T(D >= 2 ? s * (c01 * c01 + c11 * c11 + c21 * c21) : 0.0);
+  f[3 * N + q] = T(D == 3 ? s * (c02 * c02 + c12 * c12 + c22 * c22) : 0.0);
+  f[4 * N + q] = T(D >= 2 ? s * (c00 * c01 + c10 * c11 + c20 * c21) : 0.0);
+  f[5 * N + q] = T(D == 3 ? s * (c00 * c02 + c10 * c12 + c20 * c22) : 0.0);
+  f[6 * N + q] = T(D == 3 ? s * (c01 * c02 + c11 * c12 + c21 * c22) : 0.0);
+}
+
+// Mass of rational test/trial functions: entry (i, j) times w_i w_j.  One
+// workgroup per row; the row's place and its columns in closed form (CSR
+// order: j3 slowest, j1 fastest, as the pattern).
+template <typename T>
+__global__ __launch_bounds__(256) void k_nurbs_scale(PlanView v, T* __restrict__ vals) {
+  const DirView d1 = v.dir[0], d2 = v.dir[1], d3 = v.dir[2];
+  const int64_t row = blockIdx.x;
+  const int n1 = d1.n, n2 = d2.n, p = v.p;
+  const int i1 = int(row % n1), i2 = int((row / n1) % n2), i3 = int(row / (int64_t(n1) * n2));
+  int is1, ic1, is2, ic2, is3, ic3;
+  i_range(i1, p, n1, is1, ic1);
+  i_range(i2, p, n2, is2, ic2);
+  i_range(i3, p, d3.n, is3, ic3);
+  const int64_t Tn1 = d1.prefix[n1], Tn2 = d2.prefix[n2];
+  const int64_t start = d3.prefix[i3] * Tn2 * Tn1 + int64_t(ic3) * d2.prefix[i2] * Tn1 + int64_t(ic3) * ic2 * d1.prefix[i1];
+  const double wi = v.wts[row];
+  const int len = ic1 * ic2 * ic3;
+  for (int k = threadIdx.x; k < len; k += blockDim.x) {
+    const int jj1 = k % ic1, jj2 = (k / ic1) % ic2, jj3 = k / (ic1 * ic2);
+    const int64_t j = (int64_t(is3 + jj3) * n2 + (is2 + jj2)) * n1 + (is1 + jj1);
+    vals[start + k] = T(double(vals[start + k]) * (wi * v.wts[j]));
+  }
+}
+
 template <int P>
 hipError_t points_p(const PlanView& v, hipStream_t s) {
   int maxq = 0;
@@ -892,6 +1023,19 @@ hipError_t rules_p(const PlanView& v, hipStream_t s) {
 template <int P>
 hipError_t geometry_p(const PlanView& v, const double* coef, double* xphys, hipStream_t s) {
   const unsigned blocks = unsigned((v.nqtot + 255) / 256);
+  if (v.wts) {   // NURBS map
+    if (v.d == 3) {
+      if (v.prec == WQ_FP64) hipLaunchKernelGGL((k_geo_rational<P, double, 3>), dim3(blocks), dim3(256), 0, s, v, coef, xphys);
+      else hipLaunchKernelGGL((k_geo_rational<P, float, 3>), dim3(blocks), dim3(256), 0, s, v, coef, xphys);
+    } else if (v.d == 2) {
+      if (v.prec == WQ_FP64) hipLaunchKernelGGL((k_geo_rational<P, double, 2>), dim3(blocks), dim3(256), 0, s, v, coef, xphys);
+      else hipLaunchKernelGGL((k_geo_rational<P, float, 2>), dim3(blocks), dim3(256), 0, s, v, coef, xphys);
+    } else {
+      if (v.prec == WQ_FP64) hipLaunchKernelGGL((k_geo_rational<P, double, 1>), dim3(blocks), dim3(256), 0, s, v, coef, xphys);
+      else hipLaunchKernelGGL((k_geo_rational<P, float, 1>), dim3(blocks), dim3(256), 0, s, v, coef, xphys);
+    }
+    return hipGetLastError();
+  }
   if (v.d == 1) {
     if (v.prec == WQ_FP64)
       hipLaunchKernelGGL((k_geo1d<P, double>), dim3(blocks), dim3(256), 0, s, v, coef, xphys);
@@ -969,6 +1113,16 @@ hipError_t launch_scale_field(const PlanView& v, const double* coef, void* field
 hipError_t launch_qranges(const PlanView& v, int dir, int32_t* q_start, int32_t* q_count, hipStream_t s) {
   const int n = v.dir[dir].n;
   hipLaunchKernelGGL(k_qranges, dim3(unsigned((n + 255) / 256)), dim3(256), 0, s, v, dir, q_start, q_count);
+  return hipGetLastError();
+}
+
+hipError_t launch_nurbs_scale(const PlanView& v, void* vals, hipStream_t s) {
+  const int64_t rows = int64_t(v.dir[0].n) * v.dir[1].n * v.dir[2].n;
+  if (!v.wts || rows <= 0) return hipErrorInvalidValue;
+  if (v.prec == WQ_FP64)
+    hipLaunchKernelGGL(k_nurbs_scale<double>, dim3(unsigned(rows)), dim3(256), 0, s, v, static_cast<double*>(vals));
+  else
+    hipLaunchKernelGGL(k_nurbs_scale<float>, dim3(unsigned(rows)), dim3(256), 0, s, v, static_cast<float*>(vals));
   return hipGetLastError();
 }
 
