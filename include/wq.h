@@ -191,7 +191,10 @@ wq_status wq_setup_nurbs(wq_plan* plan, const double* ctrl_dev, const double* we
  * coefficient field (the geometry stage of wq_setup; the univariate rules
  * are kept); coef_dev as in wq_setup.  Requires a prior wq_setup.  Ordered
  * like every other call of the plan (see Ordering above): an assembly
- * still in flight on another stream must be waited for first. */
+ * still in flight on another stream must be waited for first, as the 3D
+ * geometry passes also use the plan's first-contraction buffer as scratch.
+ * Requests on a resident geometry (wq_assemble_request) avoid both: they
+ * bring their own field and buffer. */
 wq_status wq_set_coefficient(wq_plan* plan, const double* coef_dev, hipStream_t stream);
 
 /* Physical quadrature points F(x_q) into x_dev[n_qp3][n_qp2][n_qp1][3]

@@ -113,3 +113,36 @@ def test_nurbs_basis_refuses_stiffness_and_batches():
     b.bind([torch.empty_like(mass)], [torch.empty_like(mass)])
     with pytest.raises(WQError):
         b.assemble(1)
+
+
+def test_nurbs_through_static_request_and_batch():
+    """The other entry points on NURBS set-ups give wq_assemble's values bit
+    for bit: wq_assemble_static and wq_assemble_request with rational
+    test/trial functions (mass), and a batch of rational-map plans with
+    B-spline functions (both matrices)."""
+    import torch
+    from paper_1605_01238_amd import Batch, _wq
+    p, kn, ctrl, w = CASES["cylinder"]()
+    plan, _, _, mass, _ = nurbs_pipeline(kn, p, ctrl, w, None, 1, 1)
+    m2 = torch.full_like(mass, float("nan"))
+    st = _wq.wq_assemble_static(plan._h, 1, m2.data_ptr(), None, torch.cuda.current_stream().cuda_stream)
+    _wq.check(st, plan._h)
+    plan.sync()
+    assert torch.equal(m2, mass)
+    ctx = torch.empty(plan.request_bytes() + 256, dtype=torch.uint8, device="cuda")
+    m3, _ = plan.assemble_request(ctx, None, 1)
+    plan.sync()
+    assert torch.equal(m3, mass)
+    plans, refs = [], []
+    for name in ("annulus", "random3d_p4", "cylinder"):
+        p, kn, ctrl, w = CASES[name]()
+        pl, _, _, m, s = nurbs_pipeline(kn, p, ctrl, w, None, 3, 0)
+        plans.append(pl)
+        refs.append((m, s))
+    outs = [(torch.full_like(m, float("nan")), torch.full_like(s, float("nan"))) for m, s in refs]
+    b = Batch(plans)
+    b.bind([o[0] for o in outs], [o[1] for o in outs])
+    b.assemble(3)
+    torch.cuda.synchronize()
+    for (m, s), (m2, s2) in zip(refs, outs):
+        assert torch.equal(m, m2) and torch.equal(s, s2)
