@@ -187,6 +187,16 @@ wq_status wq_setup(wq_plan* plan, const double* ctrl_dev, const double* coef_dev
 wq_status wq_setup_nurbs(wq_plan* plan, const double* ctrl_dev, const double* weights_dev, const double* coef_dev,
                          int basis, hipStream_t stream);
 
+/* New control net on the same knots (a polynomial map; e.g. a shape
+ * update, or the next geometry of a serving loop that shares knots and
+ * degree): the geometry stage of wq_setup only — copies the net and
+ * re-forms the coefficient field; the univariate rules of the last
+ * wq_setup are kept (they depend only on the knots and p, Algorithm 2).
+ * ctrl_dev and coef_dev as in wq_setup.  Requires a prior wq_setup; ordered
+ * like every other call of the plan.
+ * Errors: WQ_EINVAL (null net), WQ_ESTATE (no wq_setup yet), WQ_EDEVICE. */
+wq_status wq_set_geometry(wq_plan* plan, const double* ctrl_dev, const double* coef_dev, hipStream_t stream);
+
 /* New diffusion coefficient a on the same geometry: recomputes the
  * coefficient field (the geometry stage of wq_setup; the univariate rules
  * are kept); coef_dev as in wq_setup.  Requires a prior wq_setup.  Ordered

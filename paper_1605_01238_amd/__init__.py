@@ -93,6 +93,14 @@ class Plan:
             raise ValueError(f"coefficient must hold {self.n_qp_total} values")
         check(_wq.wq_setup_nurbs(self._h, _ptr(ctrl), _ptr(weights), _ptr(coef), basis, _stream(stream)), self._h)
 
+    def set_geometry(self, ctrl, coef=None, stream=None):
+        """wq_set_geometry: a new control net on the same knots (rules kept)."""
+        if ctrl.numel() != self.n_rows * self.d:
+            raise ValueError(f"control net must hold {self.n_rows} x {self.d} values")
+        if coef is not None and coef.numel() != self.n_qp_total:
+            raise ValueError(f"coefficient must hold {self.n_qp_total} values")
+        check(_wq.wq_set_geometry(self._h, _ptr(ctrl), _ptr(coef), _stream(stream)), self._h)
+
     def set_coefficient(self, coef, stream=None):
         if coef is not None and coef.numel() != self.n_qp_total:
             raise ValueError(f"coefficient must hold {self.n_qp_total} values")

@@ -41,6 +41,7 @@ SIGNATURES = [
     ("wq_setup", C.c_int, [_P, _P, _P, _P]),
     ("wq_setup_nurbs", C.c_int, [_P, _P, _P, _P, C.c_int, _P]),
     ("wq_set_coefficient", C.c_int, [_P, _P, _P]),
+    ("wq_set_geometry", C.c_int, [_P, _P, _P, _P]),
     ("wq_qp_physical", C.c_int, [_P, _P, _P]),
     ("wq_pattern", C.c_int, [_P, _P, _P, _P]),
     ("wq_assemble", C.c_int, [_P, C.c_int, _P, _P, _P]),

@@ -30,6 +30,8 @@ constexpr int kWgsPerCu[] = {1, 2, 4};
 
 }  // namespace
 
+constexpr size_t kSideStreams = 4;   // streams the classes of a batch run on
+
 struct wq_batch {
   struct Class {
     int p = 0, d = 3, prec = 0;
@@ -50,9 +52,36 @@ struct wq_batch {
   hipGraphExec_t graph = nullptr;
   int graph_which = 0;
   hipStream_t graph_stream = nullptr;
+  // classes run concurrently on side streams forked from the caller's
+  // stream (a class's tail, when its queue drains, overlaps the next one)
+  std::vector<hipStream_t> side;
+  std::vector<hipEvent_t> ev_done;
+  hipEvent_t ev_fork = nullptr;
   std::string err;
   ~wq_batch() {
     if (graph) (void)hipGraphExecDestroy(graph);
+    for (hipStream_t s : side) {
+      (void)hipStreamSynchronize(s);
+      (void)hipStreamDestroy(s);
+    }
+    for (hipEvent_t e : ev_done) (void)hipEventDestroy(e);
+    if (ev_fork) (void)hipEventDestroy(ev_fork);
+  }
+  hipError_t make_side() {
+    const size_t ns = std::min<size_t>(kSideStreams, classes.size());
+    hipError_t e = hipSuccess;
+    while (e == hipSuccess && side.size() < ns) {
+      hipStream_t s = nullptr;
+      e = hipStreamCreateWithFlags(&s, hipStreamNonBlocking);
+      if (e == hipSuccess) side.push_back(s);
+    }
+    while (e == hipSuccess && ev_done.size() < classes.size()) {
+      hipEvent_t ev = nullptr;
+      e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+      if (e == hipSuccess) ev_done.push_back(ev);
+    }
+    if (e == hipSuccess && !ev_fork) e = hipEventCreateWithFlags(&ev_fork, hipEventDisableTiming);
+    return e;
   }
   void drop_graph() {
     if (graph) (void)hipGraphExecDestroy(graph);
@@ -122,19 +151,39 @@ hipError_t upload(wq_batch* b, hipStream_t s) {
   return hipMemcpyAsync(b->ws, b->img.data(), b->total_bytes, hipMemcpyHostToDevice, s);
 }
 
-// The launch sequence of one assembly (also what a captured graph holds).
+// The launches of class k (both matrices) on stream s.
+hipError_t enqueue_class(wq_batch* b, size_t k, int which, hipStream_t s) {
+  const wq_batch::Class& c = b->classes[k];
+  const wq::BatchClassView v = b->view(c);
+  hipError_t e = hipSuccess;
+  for (int stiff = 0; stiff < 2 && e == hipSuccess; ++stiff) {
+    if (!(which & (stiff ? WQ_STIFF : WQ_MASS)) || c.total[stiff] == 0) continue;
+    const int grid = std::max(1, std::min(c.total[stiff], c.wgs_per_cu * b->n_cu));
+    e = wq::launch_batch_class(v, c.p, c.d, c.prec, stiff != 0, c.first_blocks, grid, s);
+  }
+  return e;
+}
+
+// The launch sequence of one assembly (also what a captured graph holds):
+// the work-queue counters are cleared on s, then the classes run on the
+// side streams forked from s, which joins them all (one class alone, or
+// only_class for the autotuner, runs on s).
 hipError_t enqueue(wq_batch* b, int which, hipStream_t s, int only_class = -1) {
   hipError_t e = wq::launch_zero_counters(reinterpret_cast<int*>(b->ws + b->counters), int(2 * b->classes.size()), s);
-  for (size_t k = 0; k < b->classes.size() && e == hipSuccess; ++k) {
-    if (only_class >= 0 && int(k) != only_class) continue;
-    const wq_batch::Class& c = b->classes[k];
-    const wq::BatchClassView v = b->view(c);
-    for (int stiff = 0; stiff < 2 && e == hipSuccess; ++stiff) {
-      if (!(which & (stiff ? WQ_STIFF : WQ_MASS)) || c.total[stiff] == 0) continue;
-      const int grid = std::max(1, std::min(c.total[stiff], c.wgs_per_cu * b->n_cu));
-      e = wq::launch_batch_class(v, c.p, c.d, c.prec, stiff != 0, c.first_blocks, grid, s);
-    }
+  if (only_class >= 0 || b->classes.size() == 1) {
+    for (size_t k = 0; k < b->classes.size() && e == hipSuccess; ++k)
+      if (only_class < 0 || int(k) == only_class) e = enqueue_class(b, k, which, s);
+    return e;
   }
+  if (e == hipSuccess) e = b->make_side();
+  if (e == hipSuccess) e = hipEventRecord(b->ev_fork, s);
+  for (size_t j = 0; j < b->side.size() && e == hipSuccess; ++j) e = hipStreamWaitEvent(b->side[j], b->ev_fork, 0);
+  for (size_t k = 0; k < b->classes.size() && e == hipSuccess; ++k) {
+    hipStream_t sk = b->side[k % b->side.size()];
+    e = enqueue_class(b, k, which, sk);
+    if (e == hipSuccess) e = hipEventRecord(b->ev_done[k], sk);
+  }
+  for (size_t k = 0; k < b->classes.size() && e == hipSuccess; ++k) e = hipStreamWaitEvent(s, b->ev_done[k], 0);
   return e;
 }
 

@@ -302,7 +302,8 @@ static hipError_t join_rules(const wq_plan* plan, hipStream_t stream) {
 
 static const char nurbs_stiff_msg[] =
     "the stiffness of rational (NURBS) test and trial functions is not formed: set up with WQ_BASIS_BSPLINE";
-static wq_status setup_common(wq_plan* plan, const double* ctrl_dev, const double* coef_dev, hipStream_t stream);
+static wq_status setup_common(wq_plan* plan, const double* ctrl_dev, const double* coef_dev, hipStream_t stream,
+                              bool rules);
 
 wq_status wq_setup(wq_plan* plan, const double* ctrl_dev, const double* coef_dev, hipStream_t stream) {
   if (!plan) return WQ_EINVAL;
@@ -310,7 +311,16 @@ wq_status wq_setup(wq_plan* plan, const double* ctrl_dev, const double* coef_dev
   if (!ctrl_dev) return fail(plan, WQ_EINVAL, "null control net");
   plan->rational = false;
   plan->nurbs_basis = false;
-  return setup_common(plan, ctrl_dev, coef_dev, stream);
+  return setup_common(plan, ctrl_dev, coef_dev, stream, true);
+}
+
+wq_status wq_set_geometry(wq_plan* plan, const double* ctrl_dev, const double* coef_dev, hipStream_t stream) {
+  if (!plan) return WQ_EINVAL;
+  if (!plan->setup_done) return fail(plan, WQ_ESTATE, "wq_set_geometry before wq_setup");
+  if (!ctrl_dev) return fail(plan, WQ_EINVAL, "null control net");
+  plan->rational = false;
+  plan->nurbs_basis = false;
+  return setup_common(plan, ctrl_dev, coef_dev, stream, false);
 }
 
 wq_status wq_setup_nurbs(wq_plan* plan, const double* ctrl_dev, const double* weights_dev, const double* coef_dev,
@@ -326,20 +336,23 @@ wq_status wq_setup_nurbs(wq_plan* plan, const double* ctrl_dev, const double* we
   if (e != hipSuccess) return hip_fail(plan, e, "wq_setup_nurbs: weights copy");
   plan->rational = true;
   plan->nurbs_basis = basis == WQ_BASIS_NURBS;
-  return setup_common(plan, ctrl_dev, coef_dev, stream);
+  return setup_common(plan, ctrl_dev, coef_dev, stream, true);
 }
 
-static wq_status setup_common(wq_plan* plan, const double* ctrl_dev, const double* coef_dev, hipStream_t stream) {
+static wq_status setup_common(wq_plan* plan, const double* ctrl_dev, const double* coef_dev, hipStream_t stream,
+                              bool rules = true) {
   wq::PlanView v = plan->view();
   hipError_t e;
-  // univariate stage on the second stream, after everything already queued
-  // on `stream` (earlier assemblies read the tables it rewrites)
-  e = hipEventRecord(plan->ev_fork, stream);
-  if (e == hipSuccess) e = hipStreamWaitEvent(plan->aux, plan->ev_fork, 0);
-  if (e == hipSuccess) e = wq::launch_rules(v, plan->aux);
-  if (e == hipSuccess) e = hipEventRecord(plan->ev_rules, plan->aux);
-  if (e != hipSuccess) return hip_fail(plan, e, "wq_setup: univariate kernel");
-  plan->rules_launched = true;
+  if (rules) {
+    // univariate stage on the second stream, after everything already
+    // queued on `stream` (earlier assemblies read the tables it rewrites)
+    e = hipEventRecord(plan->ev_fork, stream);
+    if (e == hipSuccess) e = hipStreamWaitEvent(plan->aux, plan->ev_fork, 0);
+    if (e == hipSuccess) e = wq::launch_rules(v, plan->aux);
+    if (e == hipSuccess) e = hipEventRecord(plan->ev_rules, plan->aux);
+    if (e != hipSuccess) return hip_fail(plan, e, "wq_setup: univariate kernel");
+    plan->rules_launched = true;
+  }
   if (plan->d == 3) {
     e = wq::launch_ctrl_diff(v, ctrl_dev, stream);
   } else {   // the 1D and 2D geometry kernels read the plan's copy of the net directly

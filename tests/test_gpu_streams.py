@@ -78,3 +78,34 @@ def test_weights_read_joins_setup():
     for i in range(R.n):
         ref = R.w64[(0, 1)][i]
         assert np.abs(w[i, :qc[i]] - ref).max() <= 1e-15 * np.abs(ref).max()
+
+
+def test_set_geometry_keeps_rules_and_matches_setup():
+    """wq_set_geometry (new net, same knots, rules kept) gives the values of
+    a fresh wq_setup with that net, bit for bit, also after a NURBS set-up
+    (it returns the plan to a polynomial map)."""
+    import torch
+    from paper_1605_01238_amd import Plan
+    from workloads import coefficient_field, control_net, random_open_knots
+    p, nel = 4, (6, 7, 6)
+    kn = [random_open_knots(p, e, seed=90 + k) for k, e in enumerate(nel)]
+    nets = [torch.from_numpy(control_net(kn, p, seed=s, amp_h=0.1)).cuda() for s in (91, 92)]
+    ref = Plan(kn, p)
+    ref.bind()
+    ref.setup(nets[1])
+    m_ref, s_ref = ref.assemble(3)
+    ref.sync()
+    plan = Plan(kn, p)
+    plan.bind()
+    plan.setup(nets[0])
+    m0, s0 = plan.assemble(3)
+    plan.set_geometry(nets[1])
+    m1, s1 = plan.assemble(3)
+    w = torch.full((plan.n_rows,), 1.3, dtype=torch.float64, device="cuda")
+    plan.setup_nurbs(nets[0], w, None, 1)
+    plan.set_geometry(nets[1])
+    m2, s2 = plan.assemble(3)
+    plan.sync()
+    assert torch.equal(m1, m_ref) and torch.equal(s1, s_ref)
+    assert torch.equal(m2, m_ref) and torch.equal(s2, s_ref)
+    assert not torch.equal(s0, s_ref)
