@@ -229,6 +229,10 @@ wq_status wq_pattern(const wq_plan* plan, int64_t* row_ptr_dev, int32_t* col_idx
  *                   (WQ_FP32); required iff which has WQ_MASS, else ignored.
  *   stiff_vals_dev  likewise for WQ_STIFF.
  * Values are in the order of wq_pattern's col_idx.  Requires wq_setup.
+ * With both matrices the mass is formed on the plan's own stream (with a
+ * first-contraction buffer of its own) beside the stiffness on `stream`,
+ * which waits for it before any later work: the call is ordered on
+ * `stream` as a whole.
  * Errors: WQ_EINVAL, WQ_ESTATE, WQ_EDEVICE.
  */
 wq_status wq_assemble(wq_plan* plan, int which, void* mass_vals_dev, void* stiff_vals_dev,

@@ -130,7 +130,7 @@ struct BatchClassView {
 
 struct Layout {
   size_t knots[3], x[3], qspan[3], bv[3], bd[3], bw[3], w[3], op64[3], op32[3], bt64[3], bt32[3], wt64[3], wt32[3], prefix[3], colt64[3], colt32[3];
-  size_t field, ybuf, ctrl, dctrl, wts, flags, total;
+  size_t field, ybuf, ymass, ctrl, dctrl, wts, flags, total;
 };
 
 }  // namespace wq
@@ -152,6 +152,9 @@ struct wq_plan {
   // stream at wq_setup and joined by the calls that read its tables.
   hipStream_t aux = nullptr;
   hipEvent_t ev_fork = nullptr, ev_rules = nullptr;
+  // wq_assemble of both matrices: the mass on `aux` (with a first-contraction
+  // buffer of its own) beside the stiffness on the caller's stream
+  hipEvent_t ev_mass_fork = nullptr, ev_mass_join = nullptr;
   bool rules_launched = false;
   wq::PlanView view() const;
   ~wq_plan();

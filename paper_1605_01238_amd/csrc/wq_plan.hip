@@ -83,6 +83,8 @@ void compute_layout(wq_plan* pl) {
   const size_t ybytes = size_t(pl->n[2]) * size_t(pl->nq[1]) * size_t(pl->nq[0]) * ic * wq::kYChannels * elem;
   const size_t gbytes = size_t(pl->nq[2]) * size_t(pl->n[0]) * (size_t(pl->n[1]) + size_t(pl->nq[1])) * 9 * 8;
   L.ybuf = take(ybytes > gbytes ? ybytes : gbytes);
+  // the mass matrix's own first-contraction buffer (one channel)
+  L.ymass = take(size_t(pl->n[2]) * size_t(pl->nq[1]) * size_t(pl->nq[0]) * (pl->d == 3 ? ic : 1) * elem);
   L.ctrl = take(size_t(pl->nrows) * 3 * 8);
   L.dctrl = take(size_t(pl->nrows) * 9 * 8);
   L.wts = take(size_t(pl->nrows) * 8);
@@ -99,6 +101,8 @@ wq_plan::~wq_plan() {
   }
   if (ev_fork) (void)hipEventDestroy(ev_fork);
   if (ev_rules) (void)hipEventDestroy(ev_rules);
+  if (ev_mass_fork) (void)hipEventDestroy(ev_mass_fork);
+  if (ev_mass_join) (void)hipEventDestroy(ev_mass_join);
 }
 
 wq::PlanView wq_plan::view() const {
@@ -288,6 +292,8 @@ wq_status wq_bind(wq_plan* plan, void* workspace, size_t bytes, hipStream_t stre
     e = hipStreamCreateWithFlags(&plan->aux, hipStreamNonBlocking);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&plan->ev_fork, hipEventDisableTiming);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&plan->ev_rules, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&plan->ev_mass_fork, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&plan->ev_mass_join, hipEventDisableTiming);
     if (e != hipSuccess) return hip_fail(plan, e, "wq_bind: stream/event creation");
   }
   plan->rules_launched = false;
@@ -444,8 +450,21 @@ wq_status wq_assemble(wq_plan* plan, int which, void* mass, void* stiff, hipStre
   if (plan->nurbs_basis && (which & WQ_STIFF)) return fail(plan, WQ_EINVAL, nurbs_stiff_msg);
   hipError_t e = join_rules(plan, stream);
   if (e != hipSuccess) return hip_fail(plan, e, "wq_assemble: join");
-  e = wq::launch_assemble(plan->view(), which, mass, stiff, stream);
-  if (e == hipSuccess && plan->nurbs_basis) e = wq::launch_nurbs_scale(plan->view(), mass, stream);
+  if (which == (WQ_MASS | WQ_STIFF)) {
+    // both matrices: the mass on the plan's second stream with its own
+    // first-contraction buffer, beside the stiffness; `stream` joins it
+    wq::PlanView vm = plan->view();
+    vm.ybuf = plan->ws + plan->lay.ymass;
+    e = hipEventRecord(plan->ev_mass_fork, stream);
+    if (e == hipSuccess) e = hipStreamWaitEvent(plan->aux, plan->ev_mass_fork, 0);
+    if (e == hipSuccess) e = wq::launch_assemble(vm, WQ_MASS, mass, nullptr, plan->aux);
+    if (e == hipSuccess) e = wq::launch_assemble(plan->view(), WQ_STIFF, nullptr, stiff, stream);
+    if (e == hipSuccess) e = hipEventRecord(plan->ev_mass_join, plan->aux);
+    if (e == hipSuccess) e = hipStreamWaitEvent(stream, plan->ev_mass_join, 0);
+  } else {
+    e = wq::launch_assemble(plan->view(), which, mass, stiff, stream);
+    if (e == hipSuccess && plan->nurbs_basis) e = wq::launch_nurbs_scale(plan->view(), mass, stream);
+  }
   if (e != hipSuccess) return hip_fail(plan, e, "wq_assemble: contraction kernel");
   return WQ_OK;
 }
