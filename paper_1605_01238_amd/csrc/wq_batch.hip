@@ -175,7 +175,7 @@ hipError_t enqueue(wq_batch* b, int which, hipStream_t s, int only_class = -1) {
       if (only_class < 0 || int(k) == only_class) e = enqueue_class(b, k, which, s);
     return e;
   }
-  if (e == hipSuccess) e = b->make_side();
+  if (e == hipSuccess && b->side.empty()) e = hipErrorInvalidHandle;   // made by wq_batch_bind
   if (e == hipSuccess) e = hipEventRecord(b->ev_fork, s);
   for (size_t j = 0; j < b->side.size() && e == hipSuccess; ++j) e = hipStreamWaitEvent(b->side[j], b->ev_fork, 0);
   for (size_t k = 0; k < b->classes.size() && e == hipSuccess; ++k) {
@@ -297,6 +297,10 @@ wq_status wq_batch_bind(wq_batch* b, void* workspace, size_t bytes, void* const*
   }
   e = upload(b, stream);
   if (e != hipSuccess) return bhip(b, e, "wq_batch_bind: descriptor upload");
+  // side streams and events of the concurrent classes, made here so that
+  // a later graph capture only records work on them
+  if (b->classes.size() > 1) e = b->make_side();
+  if (e != hipSuccess) return bhip(b, e, "wq_batch_bind: side streams");
   b->bound = true;
   b->drop_graph();
   b->err.clear();
