@@ -349,7 +349,9 @@ def main():
     value = plan.nnz * n_mat / (ms_per_step * 1e-3) / 1e9
     vbytes = run.value_bytes()
     bv = vbytes // (plan.nnz * n_mat)
-    chans = (6 if run.which & 2 else 0) + (1 if run.which & 1 else 0)
+    # field channels the contraction reads: the stiffness K11..K23 (only
+    # K11, K22, K12 on a plane patch), the mass det J
+    chans = ((6 if plan.d == 3 else 3) if run.which & 2 else 0) + (1 if run.which & 1 else 0)
     read_bytes = plan.n_qp_total * chans * bv
     achieved = buf_bytes_gbs(vbytes, float(t_asm.mean()))
     fill = fill_rate_gbs(vbytes)
@@ -370,7 +372,8 @@ def main():
         "config": {"workload": w.name, "p": w.p, "n_el": list(w.n_el), "matrices": list(which_names),
                    "nnz_per_matrix": plan.nnz, "n_dof": plan.n_rows, "n_qp": plan.n_qp_total,
                    "step": "wq_setup + wq_pattern + wq_assemble", "parallelism": "single GPU"},
-        "roofline": {"bound": "hbm", "kernel": "wq_assemble (k_first + k_push per matrix)",
+        "roofline": {"bound": "hbm",
+                     "kernel": "wq_assemble (" + ("k_first + k_push" if plan.d == 3 else "k_plane") + " per matrix)",
                      "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                      "launch_ms_mean": round(float(t_asm.mean()), 4),

@@ -321,9 +321,11 @@ void wq_batch_destroy(wq_batch* batch);
  * (no hipMalloc, no allocating library routine).  Every call on one GPU
  * shares that GPU's array: calls that overlap on one GPU (different streams,
  * different plans) race and must be ordered by the caller.
- * Errors: as wq_assemble; WQ_ENOSPACE if one plane of the buffer,
- * n_qp1 * n_qp2 * (2p+1, or 1 for d < 3) * (8 channels with WQ_STIFF, else
- * 1) * value size, exceeds the array.
+ * A plane patch or curve (d < 3) has no first contraction and uses no
+ * scratch: any size is accepted.
+ * Errors: as wq_assemble; WQ_ENOSPACE (d = 3) if one plane of the buffer,
+ * n_qp1 * n_qp2 * (2p+1) * (8 channels with WQ_STIFF, else 1) * value
+ * size, exceeds the array.
  */
 #define WQ_STATIC_SCRATCH_BYTES ((size_t)64 << 20)
 wq_status wq_assemble_static(wq_plan* plan, int which, void* mass_vals_dev, void* stiff_vals_dev,

@@ -124,8 +124,7 @@ void fill_schedule(wq_batch* b, wq_batch::Class& c) {
     int acc = 0;
     for (int k = 0; k < np; ++k) {
       const wq_plan* pl = b->plans[c.members[k]];
-      const int parts = wq::push_parts(c.p, c.d, c.prec, stiff != 0);
-      const int64_t wgs = pl->n[1] * pl->n[2] * parts;
+      const int64_t wgs = wq::push_units(c.p, c.d, c.prec, stiff != 0, int(pl->n[1]), int(pl->n[2]));
       const int max_seg = std::max<int>(1, int(pl->n[0] / (2 * c.p)));
       const int64_t want = c.seg_target > 0 ? (int64_t(c.seg_target) + np * wgs - 1) / (np * wgs) : 1;
       const int nseg = int(std::min<int64_t>(max_seg, std::max<int64_t>(1, want)));
@@ -136,12 +135,13 @@ void fill_schedule(wq_batch* b, wq_batch::Class& c) {
     items[np] = acc;
     c.total[stiff] = acc;
   }
+  // first-contraction blocks (a plane class has no first contraction)
   int* blocks = reinterpret_cast<int*>(b->img.data() + c.blk);
   int acc = 0;
   for (int k = 0; k < np; ++k) {
     const wq_plan* pl = b->plans[c.members[k]];
     blocks[k] = acc;
-    acc += int(((pl->nq[0] * pl->nq[1] + 255) / 256) * pl->n[2]);
+    if (c.d == 3) acc += int(((pl->nq[0] * pl->nq[1] + 255) / 256) * pl->n[2]);
   }
   blocks[np] = acc;
   c.first_blocks = acc;

@@ -36,11 +36,16 @@
 //
 // Uniform data (operators, weights, B-spline values) is read with scalar
 // loads from tables laid out contiguously per quadrature point.
+//
+// Plane patches and curves (d <= 2) have no first contraction: a strip
+// kernel (below) reads the coefficient field directly and puts several
+// rows i2 side by side in phase C.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
 #include <climits>
 #include <mutex>
+#include <type_traits>
 
 #include "wq_internal.h"
 
@@ -60,9 +65,9 @@ enum : int { R00 = 0, R10 = 1, R01 = 2, R11 = 3 };
 // uses IC * J3 lanes); C: quadrature columns per chunk of phases A and B
 // (phase B has J3 * C * 4 items for the stiffness); WPE: waves per SIMD the
 // register allocation must allow (0: no bound).  Chosen by measurement.
-template <int P, typename T, bool STIFF, bool PLANE = false> struct PushCfg;
+template <int P, typename T, bool STIFF> struct PushCfg;
 #define WQ_PUSH_CFG(P_, T_, S_, NW_, J3_, C_, WPE_) \
-  template <> struct PushCfg<P_, T_, S_, false> { static constexpr int NW = NW_, J3 = J3_, C = C_, WPE = WPE_; };
+  template <> struct PushCfg<P_, T_, S_> { static constexpr int NW = NW_, J3 = J3_, C = C_, WPE = WPE_; };
 WQ_PUSH_CFG(2, double, false, 1, 5, 4, 0)
 WQ_PUSH_CFG(2, double, true, 1, 5, 3, 0)
 WQ_PUSH_CFG(3, double, false, 1, 7, 4, 0)
@@ -84,19 +89,13 @@ WQ_PUSH_CFG(5, float, true, 2, 11, 2, 0)
 WQ_PUSH_CFG(6, float, false, 3, 13, 8, 0)
 WQ_PUSH_CFG(6, float, true, 3, 13, 3, 0)
 #undef WQ_PUSH_CFG
-// Plane patches (d = 2: direction 3 is trivial, one j3 per pencil): one
-// wave with one j3 slot, and more quadrature columns per chunk for phase B.
-template <int P, typename T, bool STIFF>
-struct PushCfg<P, T, STIFF, true> {
-  static constexpr int NW = 1, J3 = 1, C = STIFF ? 8 : 16, WPE = 0;
-};
 
-template <int P, typename T, bool STIFF, bool PLANE = false>
+template <int P, typename T, bool STIFF>
 struct Shape {
-  using Cfg = PushCfg<P, T, STIFF, PLANE>;
+  using Cfg = PushCfg<P, T, STIFF>;
   static constexpr int IC = 2 * P + 1, QC = 3 * P + 1;
   static constexpr int NT = 64 * Cfg::NW, J3 = Cfg::J3, C = Cfg::C;
-  static constexpr int NPART = PLANE ? 1 : (IC + J3 - 1) / J3;   // j3 parts (a plane patch has one j3)
+  static constexpr int NPART = (IC + J3 - 1) / J3;        // j3 parts
   static constexpr int NG = STIFF ? 4 : 1;                // dir-1 rule groups
   static constexpr int NH = STIFF ? 6 : 1;                // merged dir-2 inputs
   static constexpr int NCH = STIFF ? 8 : 1;               // dir-3 channels
@@ -189,12 +188,10 @@ __device__ inline void store_vec(T* __restrict__ p, const T (&v)[NV]) {
 // [jj3][c], is stored contiguously for the pencil kernel.  The 64 records of
 // a wavefront are one contiguous stretch of Y; they pass through LDS so that
 // consecutive lanes store consecutive elements (whole lines per store).
-// A plane patch (PLANE: direction 3 trivial) has only j3 = 0: one slot.
-template <int P, typename T, bool STIFF, bool PLANE = false>
+template <int P, typename T, bool STIFF>
 __device__ __forceinline__ void first_body(const PlanView& v, int bx, int by) {
   constexpr int IC = 2 * P + 1, QC = 3 * P + 1, NCH = STIFF ? kYChannels : 1;
-  constexpr int ICY = PLANE ? 1 : IC;                     // j3 slots per record
-  constexpr int REC = ICY * NCH;                          // elements per record
+  constexpr int REC = IC * NCH;                           // elements per record
   constexpr int LPR = (9216 / int(sizeof(T) * REC)) < 64 ? (9216 / int(sizeof(T) * REC)) : 64;   // records per round
   __shared__ __align__(16) T stg[4][LPR * REC];
   const DirView d1 = v.dir[0], d2 = v.dir[1], d3 = v.dir[2];
@@ -207,16 +204,12 @@ __device__ __forceinline__ void first_body(const PlanView& v, int bx, int by) {
   const bool valid = l < plane;
   int qs3, qc3;
   q_range(i3, P, d3.nel, qs3, qc3);
-  if (d3.nel == 0) {   // trivial direction of a 2D problem: one point, T3^(0,0) = 1
-    qs3 = 0;
-    qc3 = 1;
-  }
   const T* __restrict__ T3 = op_t<T>(d3) + size_t(i3) * QC * IC * 4;    // [qq3][jj3][o]
   const int64_t N = v.nqtot;
   const T* __restrict__ f = static_cast<const T*>(v.field) + (valid ? l : l0) + plane * qs3;
-  T acc[ICY * NCH];
+  T acc[IC * NCH];
 #pragma unroll
-  for (int k = 0; k < ICY * NCH; ++k) acc[k] = T(0);
+  for (int k = 0; k < IC * NCH; ++k) acc[k] = T(0);
   // one quadrature point qq3: the products with the nonzero operator
   // entries jj in [lo, hi]
   auto point = [&](int qq3, int lo, int hi) {
@@ -226,7 +219,7 @@ __device__ __forceinline__ void first_body(const PlanView& v, int bx, int by) {
       const T k11 = fk[1 * N], k22 = fk[2 * N], k33 = fk[3 * N];
       const T k12 = fk[4 * N], k13 = fk[5 * N], k23 = fk[6 * N];
 #pragma unroll
-      for (int jj = 0; jj < ICY; ++jj) {
+      for (int jj = 0; jj < IC; ++jj) {
         if (jj < lo || jj > hi) continue;
         const T t0 = t[jj * 4 + R00], t1 = t[jj * 4 + R10], t2 = t[jj * 4 + R01], t3 = t[jj * 4 + R11];
         T* a = acc + jj * NCH;
@@ -242,11 +235,11 @@ __device__ __forceinline__ void first_body(const PlanView& v, int bx, int by) {
     } else {
       const T k0 = fk[0];
 #pragma unroll
-      for (int jj = 0; jj < ICY; ++jj)
+      for (int jj = 0; jj < IC; ++jj)
         if (jj >= lo && jj <= hi) acc[jj] += t[jj * 4 + R00] * k0;
     }
   };
-  if (!PLANE && i3 >= P + 1 && i3 <= d3.nel - 2) {
+  if (i3 >= P + 1 && i3 <= d3.nel - 2) {
     // row i3 away from the boundary spans: 2P+1 points alternating span
     // midpoints and knots, the operator's nonzeros in a fixed band (the
     // same products as below without the exact zeros)
@@ -254,7 +247,7 @@ __device__ __forceinline__ void first_body(const PlanView& v, int bx, int by) {
     for (int qq3 = 0; qq3 < 2 * P + 1; ++qq3) point(qq3, (qq3 + 1) / 2, qq3 / 2 + P);
   } else {
 #pragma unroll 2
-    for (int qq3 = 0; qq3 < qc3; ++qq3) point(qq3, 0, ICY - 1);
+    for (int qq3 = 0; qq3 < qc3; ++qq3) point(qq3, 0, IC - 1);
   }
   // the wave's records are contiguous in Y: pass them through LDS in rounds
   // of LPR records so that consecutive lanes store consecutive elements
@@ -274,14 +267,14 @@ __device__ __forceinline__ void first_body(const PlanView& v, int bx, int by) {
   }
 }
 
-template <int P, typename T, bool STIFF, bool PLANE = false>
+template <int P, typename T, bool STIFF>
 __global__ __launch_bounds__(256) void k_first(PlanView v) {
-  first_body<P, T, STIFF, PLANE>(v, blockIdx.x, blockIdx.y);
+  first_body<P, T, STIFF>(v, blockIdx.x, blockIdx.y);
 }
 
-template <int P, typename T, bool STIFF, bool PLANE>
+template <int P, typename T, bool STIFF>
 __device__ __forceinline__ void push_body(const PlanView& v, T* __restrict__ out, int nseg, int item) {
-  using S = Shape<P, T, STIFF, PLANE>;
+  using S = Shape<P, T, STIFF>;
   constexpr int IC = S::IC, QC = S::QC, C = S::C, NT = S::NT, J3 = S::J3;
   constexpr int NG = S::NG, NH = S::NH, NCT = S::NCT;
   __shared__ __align__(16) T hbuf[S::HSBUF];    // [C][NH][QC][J3]   (c, h, qq2, u)
@@ -316,8 +309,7 @@ __device__ __forceinline__ void push_body(const PlanView& v, T* __restrict__ out
   const int qend = e1 == nel1 - 1 ? nq1 : P + 2 * e1 + 1;
 
   constexpr int NCH = S::NCH;
-  constexpr int ICY = PLANE ? 1 : IC;   // j3 slots per Y record (a plane patch has one)
-  const T* __restrict__ Yb = static_cast<const T*>(v.ybuf) + int64_t(i3 - v.y_i3) * nq2 * nq1 * ICY * NCH;   // [q2][q1][jj3][ch]
+  const T* __restrict__ Yb = static_cast<const T*>(v.ybuf) + int64_t(i3 - v.y_i3) * nq2 * nq1 * IC * NCH;   // [q2][q1][jj3][ch]
   const T* __restrict__ w2 = wt_t<T>(d2) + size_t(i2) * QC * 4;         // [qq2][o]
   const T* __restrict__ B2 = bt_t<T>(d2) + size_t(i2) * QC * IC * 2;    // [qq2][jj2][a]
   const T* __restrict__ CT = colt_t<T>(d1);                             // [q1][NCT]
@@ -383,7 +375,7 @@ __device__ __forceinline__ void push_body(const PlanView& v, T* __restrict__ out
   for (int r = 0; r < RPL; ++r) {
     const int it = tid + r * NT;
     const int u = it % J3, c = (it / J3) % C, qq2 = it / (J3 * C);
-    roff[r] = (it < NREC && qq2 < qc2 && u < nj3) ? uint32_t(((qs2 + qq2) * nq1 + c) * ICY + j3lo + u) * NCH : ~0u;
+    roff[r] = (it < NREC && qq2 < qc2 && u < nj3) ? uint32_t(((qs2 + qq2) * nq1 + c) * IC + j3lo + u) * NCH : ~0u;
   }
   auto rec_valid = [&](int r, int col0) {
     const int c = ((tid + r * NT) / J3) % C;
@@ -392,7 +384,7 @@ __device__ __forceinline__ void push_body(const PlanView& v, T* __restrict__ out
   auto fetch = [&](int col0) {
 #pragma unroll
     for (int r = 0; r < RPL; ++r) {
-      const uint32_t off = rec_valid(r, col0) ? roff[r] + uint32_t(col0 * ICY * NCH) : 0u;
+      const uint32_t off = rec_valid(r, col0) ? roff[r] + uint32_t(col0 * IC * NCH) : 0u;
       load_vec<T, NCH>(Yb + off, pre[r]);
     }
   };
@@ -524,6 +516,326 @@ __device__ __forceinline__ void push_body(const PlanView& v, T* __restrict__ out
   for (int s = 0; s <= P; ++s) flush(e_cur + s);
 }
 
+// ---------------------------------------------------------------------------
+// Plane patches and curves (d <= 2).  Direction 3 is trivial (one point,
+// T3 = 1) and the field channels that involve it (K13, K23, K33) are zero,
+// so the first contraction would only copy the field, and each dir-1 rule
+// group of the stiffness meets exactly one input:
+//   G_(0,0) = sum_q2 B2^(1) w2^(1,1) K22     G_(1,0) = sum_q2 B2^(0) w2^(0,1) K12
+//   G_(0,1) = sum_q2 B2^(1) w2^(1,0) K12     G_(1,1) = sum_q2 B2^(0) w2^(0,0) K11
+// (the mass: G = sum_q2 B2^(0) w2^(0,0) det J).  A pencil has a single j3
+// here, so its phase C would keep 2p+1 lanes busy; instead one wave owns a
+// strip of K = floor(64 / (2p+1)) consecutive rows i2 over a run of dir-1
+// rows.  The strip's dir-2 operators and weights are copied to LDS once;
+// per chunk of C quadrature columns the field values of the strip's q2
+// window are staged in LDS (loaded during the previous chunk's phase C):
+//   phase AB (lanes: column c, half h, row slot): for the strip's rows,
+//            UB at a time, and each operator B2^(a) in turn, the group
+//            that meets B2^(a) in half h, for all j2, into LDS;
+//   phase C  (lanes: j2, row u):  the push of the pencil kernel with the K
+//            rows side by side (the column tables are shared by the strip).
+// These are the pencil kernel's products without its exact zeros, in the
+// same order.
+
+// Columns per chunk of the strip kernel.
+#ifndef WQ_PLANE_CS
+#define WQ_PLANE_CS 8
+#endif
+#ifndef WQ_PLANE_CM
+#define WQ_PLANE_CM 16
+#endif
+// Rows i2 per strip (at most floor(64/(2p+1)), the rows phase C has lanes
+// for; fewer rows use less LDS, which buys waves per compute unit).
+#ifndef WQ_PLANE_K
+#define WQ_PLANE_K 4
+#endif
+// Column tables of a chunk staged in LDS with the field tile (1) or read
+// with scalar loads per column (0).
+#ifndef WQ_PLANE_CTAB
+#define WQ_PLANE_CTAB 0
+#endif
+// Strips are split into runs of rows until the grid holds about this many
+// workgroups.
+#ifndef WQ_PLANE_WG_TARGET
+#define WQ_PLANE_WG_TARGET 4096
+#endif
+
+template <int P, typename T, bool STIFF>
+struct PlaneShape {
+  static constexpr int IC = 2 * P + 1, QC = 3 * P + 1;
+  static constexpr int ICP = IC + 1;                      // even row stride of the operator copy
+  static constexpr int K = WQ_PLANE_K > 0 && WQ_PLANE_K < 64 / IC ? WQ_PLANE_K : 64 / IC;   // rows i2 per strip
+  static constexpr int NG = STIFF ? 4 : 1;                // dir-1 rule groups
+  static constexpr int NA = STIFF ? 2 : 1;                // groups per operator (halves)
+  static constexpr int NB = STIFF ? 2 : 1;                // operators B2^(a) used
+  static constexpr int C = STIFF ? WQ_PLANE_CS : WQ_PLANE_CM;
+  static constexpr int UB = 64 / (C * NA);                // strip rows per pass of phase AB
+  static constexpr int CP = C + 1;                        // odd column strides: fewer bank conflicts
+  static constexpr int NCHT = STIFF ? 3 : 1;              // field channels in the tile
+  // q2 points of a strip: spans max(0, i2a-p) .. min(n_el-1, i2a+K-1), at
+  // most 2 per interior span and p+1 in a boundary one
+  static constexpr int WMAX = 2 * K + 4 * P - 1;
+  static constexpr size_t GBUF = size_t(NG) * K * IC * CP;
+  static constexpr size_t STAGE = size_t(K) * IC * IC;
+  static constexpr size_t TILE = size_t(NCHT) * WMAX * CP;
+  static constexpr size_t TSBUF = TILE > STAGE ? TILE : STAGE;   // the row stage shares the tile
+  static constexpr size_t BS = size_t(K) * NB * QC * ICP;
+  static constexpr size_t WS = size_t(K) * QC * 4;
+  static constexpr int NCT = 6 * (P + 1);                 // column-table entries
+  static constexpr size_t CTAB = WQ_PLANE_CTAB ? size_t(C) * NCT : 1;
+  static constexpr int TPL = int((size_t(NCHT) * WMAX * C + 63) / 64);   // tile values per lane
+  static constexpr int CPL = WQ_PLANE_CTAB ? int((CTAB + 63) / 64) : 0;   // column-table values per lane
+  static constexpr size_t LDS_BYTES = (GBUF + TSBUF + BS + WS + CTAB) * sizeof(T);
+  static_assert(C * NA * UB <= 64 && C * NA * 2 * UB > 64, "phase AB fills most of the wave");
+  static_assert(LDS_BYTES <= 64 * 1024, "LDS budget per workgroup");
+};
+
+template <int P, typename T, bool STIFF>
+__device__ __forceinline__ void plane_body(const PlanView& v, T* __restrict__ out, int nseg, int item) {
+  using S = PlaneShape<P, T, STIFF>;
+  constexpr int IC = S::IC, QC = S::QC, ICP = S::ICP, K = S::K, C = S::C, CP = S::CP, UB = S::UB;
+  constexpr int NB = S::NB, NCHT = S::NCHT, WMAX = S::WMAX, TPL = S::TPL, CPL = S::CPL, NCT = S::NCT;
+  constexpr int GSTR = K * IC * CP;   // distance between groups in the G buffer
+  const DirView d1 = v.dir[0], d2 = v.dir[1];
+  const int n1 = d1.n, n2 = d2.n, nq1 = d1.nq, nel1 = d1.nel;
+  const int tid = threadIdx.x;
+  const int nstrip = (n2 + K - 1) / K;
+  const int strip = item % nstrip, seg = item / nstrip;
+  const int i2a = strip * K;
+  const int nu = min(K, n2 - i2a);   // rows of this strip
+
+  // rows r0..r1-1 need the columns of spans e0..e1 (as for the pencils)
+  const int r0 = int(int64_t(seg) * n1 / nseg), r1 = int(int64_t(seg + 1) * n1 / nseg);
+  const int e0 = max(0, r0 - P), e1 = min(nel1 - 1, r1 - 1);
+  const int qbeg = e0 == 0 ? 0 : P + 2 * e0 - 1;
+  const int qend = e1 == nel1 - 1 ? nq1 : P + 2 * e1 + 1;
+  // q2 window of the strip: [wq0, wq0 + nw)
+  int wq0, wqc, wql, wqlc;
+  q_range(i2a, P, d2.nel, wq0, wqc);
+  q_range(i2a + nu - 1, P, d2.nel, wql, wqlc);
+  const int nw = wql + wqlc - wq0;
+
+  __shared__ __align__(16) T gbuf[S::GBUF];     // [g][u][jj2][c] (column stride CP)
+  // the field tile, [channel][q2 - wq0][c] (stride CP), is read in phase AB
+  // only; in phase C it is free and holds the row stage [u][jj2][jj1]
+  __shared__ __align__(16) T tsbuf[S::TSBUF];
+  T* const tile = tsbuf;
+  T* const stage = tsbuf;
+  __shared__ __align__(16) T bs[S::BS];         // [u][a][qq2][jj2] (stride ICP)
+  __shared__ __align__(16) T wsh[S::WS];        // [u][qq2][o]
+  __shared__ __align__(16) T ctab[S::CTAB];     // column tables of the chunk, [c][NCT]
+  const T* __restrict__ fld = static_cast<const T*>(v.field);
+  const int64_t N = v.nqtot;
+  const T* __restrict__ CT = colt_t<T>(d1);
+  const int* __restrict__ span1 = d1.qspan;
+  const int64_t Tn1 = d1.prefix[n1];
+
+  // the strip's dir-2 operators (B2^(a) rows, a-major) and weights
+  {
+    const T* __restrict__ bsrc = bt_t<T>(d2) + size_t(i2a) * QC * IC * 2;   // [u][qq2][jj2][a]
+    for (int t = tid; t < nu * QC * IC * 2; t += 64) {
+      const int a = t % 2, jj2 = (t / 2) % IC, qq2 = (t / (2 * IC)) % QC, u = t / (2 * IC * QC);
+      if (a < NB) bs[((u * NB + a) * QC + qq2) * ICP + jj2] = bsrc[t];
+    }
+    const T* __restrict__ wsrc = wt_t<T>(d2) + size_t(i2a) * QC * 4;
+    for (int t = tid; t < nu * QC * 4; t += 64) wsh[t] = wsrc[t];
+  }
+
+  // field tile and column tables of a chunk: element t = (channel, q2
+  // offset, column) and (column, entry); each lane holds TPL + CPL of them
+  // between the load and the store
+  T tpre[TPL], cpre[CPL > 0 ? CPL : 1];
+  auto tile_load = [&](int col0) {
+#pragma unroll
+    for (int k = 0; k < CPL; ++k) {
+      const int t = tid + 64 * k;
+      cpre[k] = T(0);
+      if (t < C * NCT) cpre[k] = CT[int64_t(min(col0 + t / NCT, qend - 1)) * NCT + t % NCT];
+    }
+#pragma unroll
+    for (int k = 0; k < TPL; ++k) {
+      const int t = tid + 64 * k;
+      const int ch = t / (WMAX * C), w = (t / C) % WMAX, c = t % C;
+      tpre[k] = T(0);
+      if (ch < NCHT && w < nw) {
+        const int fch = STIFF ? (ch == 0 ? 1 : (ch == 1 ? 2 : 4)) : 0;   // K11, K22, K12 / det J
+        tpre[k] = fld[fch * N + int64_t(wq0 + w) * nq1 + min(col0 + c, qend - 1)];
+      }
+    }
+  };
+  auto tile_store = [&]() {
+#pragma unroll
+    for (int k = 0; k < CPL; ++k) {
+      const int t = tid + 64 * k;
+      if (t < C * NCT) ctab[t] = cpre[k];
+    }
+#pragma unroll
+    for (int k = 0; k < TPL; ++k) {
+      const int t = tid + 64 * k;
+      const int ch = t / (WMAX * C), w = (t / C) % WMAX, c = t % C;
+      if (ch < NCHT) tile[(ch * WMAX + w) * CP + c] = tpre[k];
+    }
+  };
+
+  // phase-C role of this lane: (jj2, u)
+  const int cj2 = tid % IC, cu = tid / IC;
+  int my_ic2 = 0;
+  if (cu < nu) {
+    int is2;
+    i_range(i2a + cu, P, n2, is2, my_ic2);
+  }
+  const bool cl = cj2 < my_ic2;
+  T acc[P + 1][2 * P + 1];   // open rows e+s, s = 0..P; trial offset d = j1 - (e+s) + P
+#pragma unroll
+  for (int s = 0; s <= P; ++s)
+#pragma unroll
+    for (int d = 0; d <= 2 * P; ++d) acc[s][d] = T(0);
+
+  // row i1 (slot 0) of every row of the strip is complete: store the ones
+  // of this run, then shift the slots
+  auto flush = [&](int i1) {
+    if (i1 >= r0 && i1 < r1) {   // uniform
+      const int dlo = i1 < P ? P - i1 : 0;
+      const int dhi = min(2 * P, P + n1 - 1 - i1);
+      const int ic1 = dhi - dlo + 1;
+      if (cl) {
+        T* st = stage + cu * (IC * IC) + cj2 * ic1 - dlo;
+#pragma unroll
+        for (int d = 0; d <= 2 * P; ++d)
+          if (d >= dlo && d <= dhi) st[d] = acc[0][d];
+      }
+      __syncthreads();
+      const int64_t row1 = d1.prefix[i1];
+#pragma unroll
+      for (int u = 0; u < K; ++u) {   // uniform: one contiguous CSR row each
+        if (u < nu) {
+          const int i2 = i2a + u;
+          int is2, ic2;
+          i_range(i2, P, n2, is2, ic2);
+          T* o = out + d2.prefix[i2] * Tn1 + int64_t(ic2) * row1;
+          const int len = ic2 * ic1;
+#pragma unroll
+          for (int k = 0; k < (IC * IC + 63) / 64; ++k) {
+            const int t = tid + 64 * k;
+            if (t < len) o[t] = stage[u * (IC * IC) + t];
+          }
+        }
+      }
+      __syncthreads();
+    }
+#pragma unroll
+    for (int s = 0; s < P; ++s) {
+#pragma unroll
+      for (int d = 0; d < 2 * P - s; ++d) acc[s][d] = acc[s + 1][d];
+      acc[s][2 * P - s] = T(0);
+    }
+#pragma unroll
+    for (int d = 0; d <= P; ++d) acc[P][d] = T(0);
+  };
+
+  // phase-AB role of this lane: (column ac, half ah, row slot ab)
+  const int ac = tid % C, ah = (tid / C) % S::NA, ab = tid / (C * S::NA);
+  const bool al = ab < UB;
+
+  int e_cur = e0;
+  tile_load(qbeg);
+  tile_store();
+  __syncthreads();
+  for (int col0 = qbeg; col0 < qend; col0 += C) {
+    // ---------------- phase AB ----------------
+    for (int u0 = 0; u0 < nu; u0 += UB) {   // uniform
+      const int u = u0 + ab;
+      if (al && u < nu) {
+        const int i2 = i2a + u;
+        int qs2, qc2;
+        q_range(i2, P, d2.nel, qs2, qc2);
+        // rows whose support spans are all interior: fixed point layout and
+        // a fixed band of nonzeros in B2 (as in the pencil kernel)
+        const bool band2 = i2 >= P + 1 && i2 <= d2.nel - 2;
+        auto group = [&](auto a_) {
+          constexpr int A = decltype(a_)::value;   // the operator B2^(A)
+          constexpr int AI = NB == 2 ? A : 0;
+          // group, tile channel and dir-2 rule of the halves 0 and 1
+          constexpr int G0 = STIFF ? (A ? 0 : 1) : 0, G1 = STIFF ? (A ? 2 : 3) : 0;
+          constexpr int TC0 = STIFF ? (A ? 1 : 2) : 0, TC1 = STIFF ? (A ? 2 : 0) : 0;
+          constexpr int RL0 = STIFF ? (A ? R11 : R01) : R00, RL1 = STIFF ? (A ? R10 : R00) : R00;
+          const T* tr = tile + ((ah ? TC1 : TC0) * WMAX + (qs2 - wq0)) * CP + ac;   // + qq2 * CP
+          const T* wr = wsh + u * QC * 4 + (ah ? RL1 : RL0);                        // + qq2 * 4
+          const T* br = bs + (u * NB + AI) * QC * ICP;                               // + qq2 * ICP + jj2
+          T G[IC];
+#pragma unroll
+          for (int jj2 = 0; jj2 < IC; ++jj2) G[jj2] = T(0);
+          if (band2) {
+#pragma unroll
+            for (int qq2 = 0; qq2 < 2 * P + 1; ++qq2) {
+              const T x = wr[qq2 * 4] * tr[qq2 * CP];
+              const int lo = (qq2 + 1) / 2, hi = qq2 / 2 + P;
+#pragma unroll
+              for (int jj2 = 0; jj2 < IC; ++jj2)
+                if (jj2 >= lo && jj2 <= hi) G[jj2] = fma(br[qq2 * ICP + jj2], x, G[jj2]);
+            }
+          } else {
+            for (int qq2 = 0; qq2 < qc2; ++qq2) {
+              const T x = wr[qq2 * 4] * tr[qq2 * CP];
+#pragma unroll
+              for (int jj2 = 0; jj2 < IC; ++jj2) G[jj2] = fma(br[qq2 * ICP + jj2], x, G[jj2]);
+            }
+          }
+          T* gb = gbuf + ((ah ? G1 : G0) * K + u) * IC * CP + ac;
+#pragma unroll
+          for (int jj2 = 0; jj2 < IC; ++jj2) gb[jj2 * CP] = G[jj2];
+        };
+        if constexpr (STIFF) {
+          group(std::integral_constant<int, 1>{});
+          group(std::integral_constant<int, 0>{});
+        } else {
+          group(std::integral_constant<int, 0>{});
+        }
+      }
+    }
+    __syncthreads();
+    const bool more = col0 + C < qend;   // uniform
+    if (more) tile_load(col0 + C);       // in flight during phase C
+    // ---------------- phase C ----------------
+    for (int c = 0; c < C; ++c) {
+      const int q1c = col0 + c;
+      if (q1c >= qend) break;   // uniform
+      const int e = span1[q1c];
+      while (e_cur < e) {       // uniform; rows before e are complete
+        flush(e_cur);
+        ++e_cur;
+      }
+      if (cl) {
+        const T* ct = WQ_PLANE_CTAB ? ctab + c * NCT : CT + __builtin_amdgcn_readfirstlane(q1c * NCT);
+        const T* gb = gbuf + tid * CP + c;   // (g, u, jj2) = (g, cu, cj2)
+        if constexpr (STIFF) {
+          const T g00 = gb[0], g10 = gb[GSTR], g01 = gb[2 * GSTR], g11 = gb[3 * GSTR];
+#pragma unroll
+          for (int s = 0; s <= P; ++s) {
+            const T* w = ct + s * 4;
+            const T H0 = w[R00] * g00 + w[R01] * g01;
+            const T H1 = w[R10] * g10 + w[R11] * g11;
+#pragma unroll
+            for (int r = 0; r <= P; ++r)
+              acc[s][r - s + P] = fma(ct[5 * (P + 1) + r], H1, fma(ct[4 * (P + 1) + r], H0, acc[s][r - s + P]));
+          }
+        } else {
+          const T g0 = gb[0];
+#pragma unroll
+          for (int s = 0; s <= P; ++s) {
+            const T H0 = ct[s * 4 + R00] * g0;
+#pragma unroll
+            for (int r = 0; r <= P; ++r) acc[s][r - s + P] = fma(ct[4 * (P + 1) + r], H0, acc[s][r - s + P]);
+          }
+        }
+      }
+    }
+    if (more) tile_store();   // after the last flush of the chunk's phase C
+    __syncthreads();
+  }
+  // the rows still open
+  for (int s = 0; s <= P; ++s) flush(e_cur + s);
+}
 
 // XCD-aware order: workgroups are dealt round-robin to the 8 XCDs; give
 // each XCD a contiguous range of work items so that neighbouring pencils,
@@ -536,24 +848,37 @@ __device__ inline int xcd_item() {
 
 // The pencil kernel; configurations with WPE > 0 use the variant whose
 // register allocation is bounded for that many waves per SIMD.
-template <int P, typename T, bool STIFF, bool PLANE>
-__global__ __launch_bounds__((Shape<P, T, STIFF, PLANE>::NT)) void k_push(PlanView v, T* __restrict__ out, int nseg, int item0) {
-  push_body<P, T, STIFF, PLANE>(v, out, nseg, item0 + xcd_item());
+template <int P, typename T, bool STIFF>
+__global__ __launch_bounds__((Shape<P, T, STIFF>::NT)) void k_push(PlanView v, T* __restrict__ out, int nseg, int item0) {
+  push_body<P, T, STIFF>(v, out, nseg, item0 + xcd_item());
 }
 template <int P, typename T, bool STIFF>
 __global__ __launch_bounds__((Shape<P, T, STIFF>::NT))
 __attribute__((amdgpu_waves_per_eu(PushCfg<P, T, STIFF>::WPE))) void k_push_wpe(PlanView v, T* __restrict__ out, int nseg, int item0) {
-  push_body<P, T, STIFF, false>(v, out, nseg, item0 + xcd_item());
+  push_body<P, T, STIFF>(v, out, nseg, item0 + xcd_item());
+}
+// The strip kernel of plane patches and curves (one wave per workgroup).
+template <int P, typename T, bool STIFF>
+__global__ __launch_bounds__(64) void k_plane(PlanView v, T* __restrict__ out, int nseg) {
+  plane_body<P, T, STIFF>(v, out, nseg, xcd_item());
+}
+
+// Work units per run of rows: (pencil, j3 part) of a solid patch, strips
+// of K rows i2 of a plane patch or curve.
+template <int P, typename T, bool STIFF, bool PLANE>
+int64_t units_of(int n2, int n3) {
+  if constexpr (PLANE) return (int64_t(n2) + PlaneShape<P, T, STIFF>::K - 1) / PlaneShape<P, T, STIFF>::K * n3;
+  else return int64_t(n2) * n3 * Shape<P, T, STIFF>::NPART;
 }
 
 // ---------------------------------------------------------------------------
 // Batched form: the patches of one class (degree p, dimension d, precision)
-// of a batch, each with its own plan view, outputs and work list.  The
-// first contraction runs as one launch over all patches' blocks; the pencil
-// kernel as one persistent launch whose workgroups take (patch, work item)
-// pairs from a device queue until it is exhausted.  Work items of a patch
-// are numbered as in the single-patch launch, so each row is formed by the
-// same arithmetic in the same order.
+// of a batch, each with its own plan view, outputs and work list.  For
+// solid patches the first contraction runs as one launch over all patches'
+// blocks; the pencil (or strip) kernel as one persistent launch whose
+// workgroups take (patch, work item) pairs from a device queue until it is
+// exhausted.  Work items of a patch are numbered as in the single-patch
+// launch, so each row is formed by the same arithmetic in the same order.
 
 // largest k in [0, n) with off[k] <= x (off ascending, off[0] = 0)
 __device__ inline int find_patch(const int* __restrict__ off, int n, int x) {
@@ -566,7 +891,7 @@ __device__ inline int find_patch(const int* __restrict__ off, int n, int x) {
   return lo;
 }
 
-template <int P, typename T, bool STIFF, bool PLANE>
+template <int P, typename T, bool STIFF>
 __global__ __launch_bounds__(256) void k_first_batch(BatchClassView b) {
   __shared__ int sk;
   if (threadIdx.x == 0) sk = find_patch(b.blocks, b.np, blockIdx.x);
@@ -576,7 +901,7 @@ __global__ __launch_bounds__(256) void k_first_batch(BatchClassView b) {
   const int64_t plane = int64_t(v.dir[0].nq) * v.dir[1].nq;
   const int nbx = int((plane + 255) / 256);
   const int local = int(blockIdx.x) - b.blocks[k];
-  first_body<P, T, STIFF, PLANE>(v, local % nbx, local / nbx);
+  first_body<P, T, STIFF>(v, local % nbx, local / nbx);
 }
 
 template <int P, typename T, bool STIFF, bool PLANE>
@@ -597,12 +922,15 @@ __device__ __forceinline__ void push_batch_body(const BatchClassView& b) {
     if (w >= total) break;   // uniform: every workgroup leaves once the queue is empty
     const PlanView v = b.views[k];
     T* out = static_cast<T*>(STIFF ? b.out_stiff[k] : b.out_mass[k]);
-    push_body<P, T, STIFF, PLANE>(v, out, nsegs[k], w - items[k]);
+    if constexpr (PLANE) plane_body<P, T, STIFF>(v, out, nsegs[k], w - items[k]);
+    else push_body<P, T, STIFF>(v, out, nsegs[k], w - items[k]);
     __syncthreads();   // s_w and s_k are rewritten by the next take
   }
 }
 template <int P, typename T, bool STIFF, bool PLANE>
-__global__ __launch_bounds__((Shape<P, T, STIFF, PLANE>::NT)) void k_push_batch(BatchClassView b) {
+constexpr int batch_threads() { return PLANE ? 64 : Shape<P, T, STIFF>::NT; }
+template <int P, typename T, bool STIFF, bool PLANE>
+__global__ __launch_bounds__((batch_threads<P, T, STIFF, PLANE>())) void k_push_batch(BatchClassView b) {
   push_batch_body<P, T, STIFF, PLANE>(b);
 }
 
@@ -612,11 +940,13 @@ __global__ void k_zero_counters(int* c, int n) {
 
 template <int P, typename T, bool STIFF, bool PLANE>
 hipError_t batch_launch(const BatchClassView& b, int first_blocks, int grid, hipStream_t s) {
-  if (first_blocks > 0)
-    hipLaunchKernelGGL((k_first_batch<P, T, STIFF, PLANE>), dim3(unsigned(first_blocks)), dim3(256), 0, s, b);
+  if constexpr (!PLANE) {
+    if (first_blocks > 0)
+      hipLaunchKernelGGL((k_first_batch<P, T, STIFF>), dim3(unsigned(first_blocks)), dim3(256), 0, s, b);
+  }
   // (the persistent loop needs more registers than one pencil: the bounds
   // of the single-patch configurations would make it spill)
-  hipLaunchKernelGGL((k_push_batch<P, T, STIFF, PLANE>), dim3(unsigned(grid)), dim3(Shape<P, T, STIFF, PLANE>::NT), 0, s, b);
+  hipLaunchKernelGGL((k_push_batch<P, T, STIFF, PLANE>), dim3(unsigned(grid)), dim3(batch_threads<P, T, STIFF, PLANE>()), 0, s, b);
   return hipGetLastError();
 }
 
@@ -633,25 +963,23 @@ hipError_t batch_p(const BatchClassView& b, int d, int prec, bool stiff, int fir
                          : batch_pt<P, float>(b, d, stiff, first_blocks, grid, s);
 }
 
-template <int P, typename T, bool STIFF, bool PLANE>
-constexpr int parts_of() { return Shape<P, T, STIFF, PLANE>::NPART; }
 template <int P>
-int parts_p(int d, int prec, bool stiff) {
+int64_t units_p(int d, int prec, bool stiff, int n2, int n3) {
   if (prec == WQ_FP64) {
-    if (stiff) return d <= 2 ? parts_of<P, double, true, true>() : parts_of<P, double, true, false>();
-    return d <= 2 ? parts_of<P, double, false, true>() : parts_of<P, double, false, false>();
+    if (stiff) return d <= 2 ? units_of<P, double, true, true>(n2, n3) : units_of<P, double, true, false>(n2, n3);
+    return d <= 2 ? units_of<P, double, false, true>(n2, n3) : units_of<P, double, false, false>(n2, n3);
   }
-  if (stiff) return d <= 2 ? parts_of<P, float, true, true>() : parts_of<P, float, true, false>();
-  return d <= 2 ? parts_of<P, float, false, true>() : parts_of<P, float, false, false>();
+  if (stiff) return d <= 2 ? units_of<P, float, true, true>(n2, n3) : units_of<P, float, true, false>(n2, n3);
+  return d <= 2 ? units_of<P, float, false, true>(n2, n3) : units_of<P, float, false, false>(n2, n3);
 }
 
 // The rows of the pencils with i3 in [i3a, i3b): k_first fills the Y planes
 // of that slab (v.ybuf holds the planes from v.y_i3 on), k_push forms them.
 // Workgroups are ordered i3 slowest, so a slab is a contiguous item range.
-template <int P, typename T, bool STIFF, bool PLANE>
+template <int P, typename T, bool STIFF>
 hipError_t push_launch(const PlanView& v, void* out, hipStream_t s, int i3a, int i3b) {
-  using Sh = Shape<P, T, STIFF, PLANE>;
-  const int64_t wgs = int64_t(v.dir[1].n) * v.dir[2].n * Sh::NPART;
+  using Sh = Shape<P, T, STIFF>;
+  const int64_t wgs = units_of<P, T, STIFF, false>(v.dir[1].n, v.dir[2].n);
   // runs of at least 2p rows
   const int max_seg = std::max(1, v.dir[0].n / (2 * P));
   const int nseg = int(std::min<int64_t>(max_seg, std::max<int64_t>(1, (WQ_WG_TARGET + wgs - 1) / wgs)));
@@ -660,26 +988,37 @@ hipError_t push_launch(const PlanView& v, void* out, hipStream_t s, int i3a, int
   const int64_t per_i3 = items / v.dir[2].n;
   const int64_t plane = int64_t(v.dir[0].nq) * v.dir[1].nq;
   if (i3b <= i3a) return hipSuccess;
-  hipLaunchKernelGGL((k_first<P, T, STIFF, PLANE>), dim3(unsigned((plane + 255) / 256), unsigned(i3b - i3a)), dim3(256), 0, s, v);
+  hipLaunchKernelGGL((k_first<P, T, STIFF>), dim3(unsigned((plane + 255) / 256), unsigned(i3b - i3a)), dim3(256), 0, s, v);
   const dim3 grid(unsigned(per_i3 * (i3b - i3a)));
   const int item0 = int(per_i3 * i3a);
-  if constexpr (PushCfg<P, T, STIFF, PLANE>::WPE > 0)
+  if constexpr (PushCfg<P, T, STIFF>::WPE > 0)
     hipLaunchKernelGGL((k_push_wpe<P, T, STIFF>), grid, dim3(Sh::NT), 0, s, v, static_cast<T*>(out), nseg, item0);
   else
-    hipLaunchKernelGGL((k_push<P, T, STIFF, PLANE>), grid, dim3(Sh::NT), 0, s, v, static_cast<T*>(out), nseg, item0);
+    hipLaunchKernelGGL((k_push<P, T, STIFF>), grid, dim3(Sh::NT), 0, s, v, static_cast<T*>(out), nseg, item0);
+  return hipGetLastError();
+}
+
+// All rows of a plane patch or curve: the strip kernel alone (it reads the
+// coefficient field directly; no first-contraction buffer).
+template <int P, typename T, bool STIFF>
+hipError_t plane_launch(const PlanView& v, void* out, hipStream_t s) {
+  const int64_t wgs = units_of<P, T, STIFF, true>(v.dir[1].n, v.dir[2].n);
+  const int max_seg = std::max(1, v.dir[0].n / (2 * P));
+  const int nseg = int(std::min<int64_t>(max_seg, std::max<int64_t>(1, (WQ_PLANE_WG_TARGET + wgs - 1) / wgs)));
+  const int64_t items = wgs * nseg;
+  if (items <= 0 || items > INT32_MAX) return hipErrorInvalidConfiguration;
+  hipLaunchKernelGGL((k_plane<P, T, STIFF>), dim3(unsigned(items)), dim3(64), 0, s, v, static_cast<T*>(out), nseg);
   return hipGetLastError();
 }
 
 template <int P, typename T>
 hipError_t assemble_pt(const PlanView& v, int which, void* mass, void* stiff, hipStream_t s, int i3a, int i3b) {
   if (which & WQ_MASS) {
-    hipError_t e = v.d <= 2 ? push_launch<P, T, false, true>(v, mass, s, i3a, i3b)
-                            : push_launch<P, T, false, false>(v, mass, s, i3a, i3b);
+    hipError_t e = v.d <= 2 ? plane_launch<P, T, false>(v, mass, s) : push_launch<P, T, false>(v, mass, s, i3a, i3b);
     if (e != hipSuccess) return e;
   }
   if (which & WQ_STIFF) {
-    hipError_t e = v.d <= 2 ? push_launch<P, T, true, true>(v, stiff, s, i3a, i3b)
-                            : push_launch<P, T, true, false>(v, stiff, s, i3a, i3b);
+    hipError_t e = v.d <= 2 ? plane_launch<P, T, true>(v, stiff, s) : push_launch<P, T, true>(v, stiff, s, i3a, i3b);
     if (e != hipSuccess) return e;
   }
   return hipSuccess;
@@ -754,25 +1093,27 @@ hipError_t launch_zero_counters(int* c, int n, hipStream_t s) {
   return hipGetLastError();
 }
 
-int push_parts(int p, int d, int prec, bool stiff) {
+int64_t push_units(int p, int d, int prec, bool stiff, int n2, int n3) {
   switch (p) {
-    case 2: return parts_p<2>(d, prec, stiff);
-    case 3: return parts_p<3>(d, prec, stiff);
-    case 4: return parts_p<4>(d, prec, stiff);
-    case 5: return parts_p<5>(d, prec, stiff);
-    case 6: return parts_p<6>(d, prec, stiff);
-    default: return 1;
+    case 2: return units_p<2>(d, prec, stiff, n2, n3);
+    case 3: return units_p<3>(d, prec, stiff, n2, n3);
+    case 4: return units_p<4>(d, prec, stiff, n2, n3);
+    case 5: return units_p<5>(d, prec, stiff, n2, n3);
+    case 6: return units_p<6>(d, prec, stiff, n2, n3);
+    default: return 0;
   }
 }
 
 size_t static_plane_bytes(const PlanView& v, int which) {
+  if (v.d <= 2) return 0;   // the strip kernel needs no first-contraction buffer
   const size_t elem = v.prec == WQ_FP64 ? 8 : 4;
-  const size_t icy = v.d <= 2 ? 1 : size_t(icap_of(v.p));
+  const size_t icy = size_t(icap_of(v.p));
   const size_t nch = (which & WQ_STIFF) ? size_t(kYChannels) : 1;
   return size_t(v.dir[0].nq) * size_t(v.dir[1].nq) * icy * nch * elem;
 }
 
 hipError_t launch_assemble_static(const PlanView& v, int which, void* mass, void* stiff, hipStream_t s) {
+  if (v.d <= 2) return assemble_slab(v, which, mass, stiff, s, 0, 1);   // no scratch used
   const size_t pb = static_plane_bytes(v, which);
   const int per_slab = int(std::min<size_t>(kStaticScratchBytes / pb, size_t(v.dir[2].n)));
   if (per_slab < 1) return hipErrorInvalidValue;   // refused by the caller beforehand

@@ -176,15 +176,19 @@ hipError_t launch_nurbs_scale(const PlanView& v, void* vals, hipStream_t s);
 hipError_t launch_scale_field(const PlanView& v, const double* coef, void* field_out, hipStream_t s);
 hipError_t launch_assemble(const PlanView& v, int which, void* mass, void* stiff, hipStream_t s);
 // The same rows with the first-contraction buffer in the library's static
-// scratch, i3 plane slab by slab (no allocation of any kind).
+// scratch, i3 plane slab by slab (no allocation of any kind; a plane patch
+// or curve uses no buffer).
 hipError_t launch_assemble_static(const PlanView& v, int which, void* mass, void* stiff, hipStream_t s);
-// Bytes of one first-contraction plane (one i3) for the matrices of `which`.
+// Bytes of one first-contraction plane (one i3) for the matrices of `which`
+// (0 for d <= 2: no first contraction there).
 size_t static_plane_bytes(const PlanView& v, int which);
 // Batched form: one class of patches (first contraction over all blocks,
 // then the persistent pencil kernel with `grid` workgroups).
 hipError_t launch_batch_class(const BatchClassView& b, int p, int d, int prec, bool stiff, int first_blocks,
                               int grid, hipStream_t s);
 hipError_t launch_zero_counters(int* c, int n, hipStream_t s);
-// j3 parts per pencil of the pencil kernel for (p, d, precision, matrix).
-int push_parts(int p, int d, int prec, bool stiff);
+// Work units per run of rows for (p, d, precision, matrix) on a patch with
+// n2 x n3 pencils: (pencil, j3 part) pairs of a solid patch, strips of rows
+// i2 of a plane patch or curve.
+int64_t push_units(int p, int d, int prec, bool stiff, int n2, int n3);
 }  // namespace wq

@@ -83,8 +83,9 @@ void compute_layout(wq_plan* pl) {
   const size_t ybytes = size_t(pl->n[2]) * size_t(pl->nq[1]) * size_t(pl->nq[0]) * ic * wq::kYChannels * elem;
   const size_t gbytes = size_t(pl->nq[2]) * size_t(pl->n[0]) * (size_t(pl->n[1]) + size_t(pl->nq[1])) * 9 * 8;
   L.ybuf = take(ybytes > gbytes ? ybytes : gbytes);
-  // the mass matrix's own first-contraction buffer (one channel)
-  L.ymass = take(size_t(pl->n[2]) * size_t(pl->nq[1]) * size_t(pl->nq[0]) * (pl->d == 3 ? ic : 1) * elem);
+  // the mass matrix's own first-contraction buffer (one channel; a plane
+  // patch or curve has no first contraction)
+  L.ymass = take(pl->d == 3 ? size_t(pl->n[2]) * size_t(pl->nq[1]) * size_t(pl->nq[0]) * ic * elem : 0);
   L.ctrl = take(size_t(pl->nrows) * 3 * 8);
   L.dctrl = take(size_t(pl->nrows) * 9 * 8);
   L.wts = take(size_t(pl->nrows) * 8);
@@ -385,8 +386,10 @@ wq_status wq_set_coefficient(wq_plan* plan, const double* coef_dev, hipStream_t 
 static void request_layout(const wq_plan* plan, size_t* field_off, size_t* y_off, size_t* total) {
   const size_t elem = plan->prec == WQ_FP64 ? 8 : 4;
   const size_t fbytes = size_t(wq::kNumChannels) * size_t(plan->nqtot) * elem;
-  const size_t ybytes = size_t(plan->n[2]) * size_t(plan->nq[1]) * size_t(plan->nq[0]) *
-                        (plan->d == 3 ? size_t(wq::icap_of(plan->p)) : 1) * wq::kYChannels * elem;
+  // (the strip kernel of a plane patch or curve reads the field directly)
+  const size_t ybytes = plan->d == 3 ? size_t(plan->n[2]) * size_t(plan->nq[1]) * size_t(plan->nq[0]) *
+                                           size_t(wq::icap_of(plan->p)) * wq::kYChannels * elem
+                                     : 0;
   *field_off = 0;
   *y_off = align256(fbytes);
   *total = *y_off + align256(ybytes);

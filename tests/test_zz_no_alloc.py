@@ -64,6 +64,8 @@ def test_static_scratch_matches_workspace_assembly(precision):
 
 
 def test_static_scratch_plane_patch():
+    """A plane patch has no first contraction: the static call uses no
+    scratch and gives wq_assemble's values."""
     import torch
     plan, mass, stiff, m2, s2 = _case(5, (40, 33), 12, 0, coef_seed=13)
     print("[no-alloc] plane p=5 n_el=(40, 33)", flush=True)
