@@ -114,7 +114,9 @@ typedef struct {
  *              values in FP64.  WQ_FP32: the same in FP32 ("FP32 bulk"),
  *              while weights, det J and J^{-1} are still computed in FP64.
  *   out        receives the plan (NULL on error).
- * Errors: WQ_EINVAL, WQ_EKNOTS.
+ * Errors: WQ_EINVAL (also for a patch beyond the kernels' 32-bit index
+ * limits: N_DOF or N_QP of 2^31 or more, or, for d = 3, n_qp1 * n_qp2 *
+ * (2p+1) * 8 of 2^32 or more), WQ_EKNOTS.
  */
 wq_status wq_plan_create(int d, int p, const int64_t* n_knots, const double* const* knots,
                          int precision, wq_plan** out);

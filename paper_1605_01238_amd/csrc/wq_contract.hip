@@ -806,7 +806,7 @@ __device__ __forceinline__ void plane_body(const PlanView& v, T* __restrict__ ou
         ++e_cur;
       }
       if (cl) {
-        const T* ct = WQ_PLANE_CTAB ? ctab + c * NCT : CT + __builtin_amdgcn_readfirstlane(q1c * NCT);
+        const T* ct = WQ_PLANE_CTAB ? ctab + c * NCT : CT + int64_t(__builtin_amdgcn_readfirstlane(q1c)) * NCT;
         const T* gb = gbuf + tid * CP + c;   // (g, u, jj2) = (g, cu, cj2)
         if constexpr (STIFF) {
           const T g00 = gb[0], g10 = gb[GSTR], g01 = gb[2 * GSTR], g11 = gb[3 * GSTR];

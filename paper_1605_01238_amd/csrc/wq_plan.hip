@@ -191,12 +191,13 @@ wq_status wq_plan_create(int d, int p, const int64_t* n_knots, const double* con
   }
   // 32-bit index limits of the kernels: column and quadrature-point indices,
   // and element offsets within one i3 plane of the first-contraction buffer
+  // (solid patches only: plane patches and curves have none)
   if (nrows >= (int64_t(1) << 31) || nqtot >= (int64_t(1) << 31)) {
     delete pl;
     return create_fail(WQ_EINVAL, "patch too large: N_DOF and N_QP must stay below 2^31");
   }
-  const int64_t yplane = pl->nq[0] * pl->nq[1] * (d == 3 ? wq::icap_of(p) : 1) * wq::kYChannels;
-  if (yplane >= (int64_t(1) << 32)) {
+  const int64_t yplane = pl->nq[0] * pl->nq[1] * wq::icap_of(p) * wq::kYChannels;
+  if (d == 3 && yplane >= (int64_t(1) << 32)) {
     delete pl;
     return create_fail(WQ_EINVAL, "patch too large: n_qp1 * n_qp2 * (2p+1) * 8 must stay below 2^32");
   }

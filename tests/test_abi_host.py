@@ -180,6 +180,18 @@ def test_first_contraction_offset_limit():
     _wq.wq_plan_destroy(h)
 
 
+def test_plane_patch_has_no_first_contraction_limit():
+    """Plane patches have no first-contraction buffer, so only the N_DOF and
+    N_QP limits apply: a plane whose n_qp1 n_qp2 8 reaches 2^32 is accepted."""
+    from paper_1605_01238_amd import _wq
+    from workloads import open_uniform_knots
+    p = 2
+    kn = open_uniform_knots(p, 12000)    # n_qp = 24003: 24003^2 * 8 > 2^32, N_QP = 24003^2 < 2^31
+    st, h = make([kn, kn], p)
+    assert st == 0, _wq.wq_last_error(None)
+    _wq.wq_plan_destroy(h)
+
+
 def test_static_scratch_size_matches_header():
     import re
     from paper_1605_01238_amd import _wq
