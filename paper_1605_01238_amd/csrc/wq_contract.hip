@@ -525,10 +525,11 @@ __device__ __forceinline__ void push_body(const PlanView& v, T* __restrict__ out
 //   G_(0,1) = sum_q2 B2^(1) w2^(1,0) K12     G_(1,1) = sum_q2 B2^(0) w2^(0,0) K11
 // (the mass: G = sum_q2 B2^(0) w2^(0,0) det J).  A pencil has a single j3
 // here, so its phase C would keep 2p+1 lanes busy; instead one wave owns a
-// strip of K = floor(64 / (2p+1)) consecutive rows i2 over a run of dir-1
-// rows.  The strip's dir-2 operators and weights are copied to LDS once;
-// per chunk of C quadrature columns the field values of the strip's q2
-// window are staged in LDS (loaded during the previous chunk's phase C):
+// strip of K consecutive rows i2 (at most floor(64 / (2p+1))) over a run
+// of dir-1 rows.  The strip's dir-2 operators and weights are copied to LDS
+// once; per chunk of C quadrature columns the field values of the strip's
+// q2 window are staged in LDS (loaded during the previous chunk's phase C,
+// or after it where registers are short):
 //   phase AB (lanes: column c, half h, row slot): for the strip's rows,
 //            UB at a time, and each operator B2^(a) in turn, the group
 //            that meets B2^(a) in half h, for all j2, into LDS;
@@ -564,7 +565,13 @@ template <int P, typename T, bool STIFF>
 struct PlaneShape {
   static constexpr int IC = 2 * P + 1, QC = 3 * P + 1;
   static constexpr int ICP = IC + 1;                      // even row stride of the operator copy
-  static constexpr int K = WQ_PLANE_K > 0 && WQ_PLANE_K < 64 / IC ? WQ_PLANE_K : 64 / IC;   // rows i2 per strip
+  // the p = 6 FP64 stiffness (phase-C accumulators alone 182 VGPRs) takes
+  // 2 rows and a bound of 2 waves per SIMD: with 4 rows its LDS and
+  // registers left one wave per SIMD
+  static constexpr bool TIGHT = P == 6 && STIFF && sizeof(T) == 8;
+  static constexpr int KW = TIGHT ? 2 : WQ_PLANE_K;
+  static constexpr int K = KW > 0 && KW < 64 / IC ? KW : 64 / IC;   // rows i2 per strip
+  static constexpr int WPE = TIGHT ? 2 : 0;                          // waves per SIMD bound
   static constexpr int NG = STIFF ? 4 : 1;                // dir-1 rule groups
   static constexpr int NA = STIFF ? 2 : 1;                // groups per operator (halves)
   static constexpr int NB = STIFF ? 2 : 1;                // operators B2^(a) used
@@ -585,6 +592,10 @@ struct PlaneShape {
   static constexpr size_t CTAB = WQ_PLANE_CTAB ? size_t(C) * NCT : 1;
   static constexpr int TPL = int((size_t(NCHT) * WMAX * C + 63) / 64);   // tile values per lane
   static constexpr int CPL = WQ_PLANE_CTAB ? int((CTAB + 63) / 64) : 0;   // column-table values per lane
+  // FP64 at p >= 4: fewer live registers (the next tile is loaded after
+  // phase C instead of during it, and rows are stored one strip row at a
+  // time), which buys a wave per SIMD where the count crosses 128 or 256
+  static constexpr bool LEAN = sizeof(T) == 8 && P >= 4;
   static constexpr size_t LDS_BYTES = (GBUF + TSBUF + BS + WS + CTAB) * sizeof(T);
   static_assert(C * NA * UB <= 64 && C * NA * 2 * UB > 64, "phase AB fills most of the wave");
   static_assert(LDS_BYTES <= 64 * 1024, "LDS budget per workgroup");
@@ -706,7 +717,7 @@ __device__ __forceinline__ void plane_body(const PlanView& v, T* __restrict__ ou
       }
       __syncthreads();
       const int64_t row1 = d1.prefix[i1];
-#pragma unroll
+#pragma unroll(S::LEAN ? 1 : K)
       for (int u = 0; u < K; ++u) {   // uniform: one contiguous CSR row each
         if (u < nu) {
           const int i2 = i2a + u;
@@ -795,7 +806,7 @@ __device__ __forceinline__ void plane_body(const PlanView& v, T* __restrict__ ou
     }
     __syncthreads();
     const bool more = col0 + C < qend;   // uniform
-    if (more) tile_load(col0 + C);       // in flight during phase C
+    if (!S::LEAN && more) tile_load(col0 + C);   // in flight during phase C
     // ---------------- phase C ----------------
     for (int c = 0; c < C; ++c) {
       const int q1c = col0 + c;
@@ -830,6 +841,7 @@ __device__ __forceinline__ void plane_body(const PlanView& v, T* __restrict__ ou
         }
       }
     }
+    if (S::LEAN && more) tile_load(col0 + C);
     if (more) tile_store();   // after the last flush of the chunk's phase C
     __syncthreads();
   }
@@ -859,7 +871,8 @@ __attribute__((amdgpu_waves_per_eu(PushCfg<P, T, STIFF>::WPE))) void k_push_wpe(
 }
 // The strip kernel of plane patches and curves (one wave per workgroup).
 template <int P, typename T, bool STIFF>
-__global__ __launch_bounds__(64) void k_plane(PlanView v, T* __restrict__ out, int nseg) {
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(PlaneShape<P, T, STIFF>::WPE)))
+void k_plane(PlanView v, T* __restrict__ out, int nseg) {
   plane_body<P, T, STIFF>(v, out, nseg, xcd_item());
 }
 
