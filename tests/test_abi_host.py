@@ -228,3 +228,25 @@ def test_batch_host_calls_without_device():
     assert _wq.wq_batch_create(0, arr, C.byref(b)) == _wq.WQ_EINVAL
     for h in hs:
         _wq.wq_plan_destroy(h)
+
+
+def test_strip_q2_window_bound():
+    """The strip kernel of plane patches stages, per strip of K consecutive
+    rows i2, the union of their point sets Q_i2 (Section 4, Remark 4.1
+    layout) in a tile sized for 2K + 4p - 1 points.  Checked here on the
+    oracle's exact point sets for every K the kernel can take."""
+    from oracle.rules import point_set, quadrature_points
+    from oracle.splines import exact_knots
+    from workloads import open_uniform_knots, random_open_knots
+    for p in range(2, 7):
+        for nel in (p + 2, p + 3, 2 * p + 3, 23):
+            for kn in (open_uniform_knots(p, nel), random_open_knots(p, nel, seed=nel)):
+                knots = exact_knots(kn)
+                pts = quadrature_points(knots, p)
+                n = len(knots) - p - 1
+                sets = [point_set(knots, p, pts, i) for i in range(n)]
+                for K in range(1, 64 // (2 * p + 1) + 1):
+                    for a in range(0, n, K):
+                        window = set().union(*sets[a:a + K])
+                        assert max(window) - min(window) + 1 <= 2 * K + 4 * p - 1, (p, nel, K, a)
+                        assert len(window) == max(window) - min(window) + 1   # contiguous
