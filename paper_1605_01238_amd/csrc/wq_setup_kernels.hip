@@ -576,15 +576,19 @@ __device__ inline int div_small(int t, int d, float inv) {
 }
 
 // ---------------------------------------------------------------------------
-// CSR pattern: one wavefront per row.  A row's columns are (j3, j2, j1)
-// lexicographic.  Lanes write 16-byte groups of 4 consecutive entries (the
-// first group starts at the first 16-byte boundary of the row; the few
-// entries before it and after the last full group are written singly).
+// CSR pattern: LW lanes per row (a wavefront for the long rows of a solid
+// patch, a quarter of one for the short rows of a plane patch or curve).
+// A row's columns are (j3, j2, j1) lexicographic.  Lanes write 16-byte
+// groups of 4 consecutive entries (the first group starts at the first
+// 16-byte boundary of the row; the few entries before it and after the last
+// full group are written singly).
+template <int LW>
 __global__ __launch_bounds__(256) void k_pattern(PlanView v, int64_t* __restrict__ row_ptr,
                                                  int32_t* __restrict__ col_idx) {
-  const int lane = threadIdx.x & 63;
-  // one row per wavefront: the row and everything derived from it are uniform
-  const int64_t row = int64_t(blockIdx.x) * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int lane = threadIdx.x % LW;
+  // with one row per wavefront the row and everything derived from it are uniform
+  const int64_t row = int64_t(blockIdx.x) * (256 / LW) +
+                      (LW == 64 ? __builtin_amdgcn_readfirstlane(threadIdx.x / LW) : int(threadIdx.x / LW));
   const DirView d1 = v.dir[0], d2 = v.dir[1], d3 = v.dir[2];
   const int n1 = d1.n, n2 = d2.n, n3 = d3.n;
   const int64_t nrows = int64_t(n1) * n2 * n3;
@@ -621,13 +625,14 @@ __global__ __launch_bounds__(256) void k_pattern(PlanView v, int64_t* __restrict
   if (lane < head) col_idx[start + lane] = col_of(lane);
   const int tail0 = head + 4 * ngroups;
   if (lane < len - tail0) col_idx[start + tail0 + lane] = col_of(tail0 + lane);
-  // 16-byte groups: lane takes groups lane, lane+64, ...; its position moves
-  // by 256 entries per step, (s3, s2, s1) in the row's mixed radix
-  const int s3 = 256 / plane, s2 = (256 - s3 * plane) / ic1, s1 = 256 - s3 * plane - s2 * ic1;
+  // 16-byte groups: lane takes groups lane, lane+LW, ...; its position moves
+  // by 4 LW entries per step, (s3, s2, s1) in the row's mixed radix
+  constexpr int STEP = 4 * LW;
+  const int s3 = STEP / plane, s2 = (STEP - s3 * plane) / ic1, s1 = STEP - s3 * plane - s2 * ic1;
   int jj3, jj2, jj1;
   split(head + 4 * lane, jj3, jj2, jj1);
   int4* __restrict__ o = reinterpret_cast<int4*>(col_idx + start + head);
-  for (int g = lane; g < ngroups; g += 64) {
+  for (int g = lane; g < ngroups; g += LW) {
     int c[4];
     int a1 = jj1, a2 = jj2, a3 = jj3;
 #pragma unroll
@@ -1139,7 +1144,10 @@ hipError_t launch_ctrl_diff(const PlanView& v, const double* ctrl, hipStream_t s
 
 hipError_t launch_pattern(const PlanView& v, int64_t* row_ptr, int32_t* col_idx, hipStream_t s) {
   const int64_t nrows = int64_t(v.dir[0].n) * v.dir[1].n * v.dir[2].n;
-  hipLaunchKernelGGL(k_pattern, dim3(unsigned((nrows + 3) / 4)), dim3(256), 0, s, v, row_ptr, col_idx);
+  if (v.d == 3)
+    hipLaunchKernelGGL(k_pattern<64>, dim3(unsigned((nrows + 3) / 4)), dim3(256), 0, s, v, row_ptr, col_idx);
+  else
+    hipLaunchKernelGGL(k_pattern<16>, dim3(unsigned((nrows + 15) / 16)), dim3(256), 0, s, v, row_ptr, col_idx);
   return hipGetLastError();
 }
 
