@@ -128,6 +128,11 @@ __device__ inline const T* bt_t(const DirView& d) {
   else return reinterpret_cast<const T*>(d.bt32);
 }
 template <typename T>
+__device__ inline const T* b0t_t(const DirView& d) {
+  if constexpr (sizeof(T) == 8) return reinterpret_cast<const T*>(d.b0t64);
+  else return reinterpret_cast<const T*>(d.b0t32);
+}
+template <typename T>
 __device__ inline const T* wt_t(const DirView& d) {
   if constexpr (sizeof(T) == 8) return reinterpret_cast<const T*>(d.wt64);
   else return reinterpret_cast<const T*>(d.wt32);
@@ -311,7 +316,9 @@ __device__ __forceinline__ void push_body(const PlanView& v, T* __restrict__ out
   constexpr int NCH = S::NCH;
   const T* __restrict__ Yb = static_cast<const T*>(v.ybuf) + int64_t(i3 - v.y_i3) * nq2 * nq1 * IC * NCH;   // [q2][q1][jj3][ch]
   const T* __restrict__ w2 = wt_t<T>(d2) + size_t(i2) * QC * 4;         // [qq2][o]
-  const T* __restrict__ B2 = bt_t<T>(d2) + size_t(i2) * QC * IC * 2;    // [qq2][jj2][a]
+  // [qq2][jj2][a] for the stiffness, [qq2][jj2] (B2^(0) alone, contiguous) for the mass
+  const T* __restrict__ B2 = STIFF ? bt_t<T>(d2) + size_t(i2) * QC * IC * 2 : b0t_t<T>(d2) + size_t(i2) * QC * IC;
+  constexpr int BQ = STIFF ? IC * 2 : IC, BJ = STIFF ? 2 : 1;   // strides of qq2 and jj2 in B2
   const T* __restrict__ CT = colt_t<T>(d1);                             // [q1][NCT]
   const int* __restrict__ span1 = d1.qspan;
 
@@ -449,13 +456,13 @@ __device__ __forceinline__ void push_body(const PlanView& v, T* __restrict__ out
         for (int qq2 = 0; qq2 < 2 * P + 1; ++qq2) {
           const T x0 = hb0[qq2 * J3];
           const T x1 = STIFF ? hb1[qq2 * J3] : T(0);
-          const T* b = B2 + qq2 * IC * 2;
+          const T* b = B2 + qq2 * BQ;
           const int lo = (qq2 + 1) / 2, hi = qq2 / 2 + P;
 #pragma unroll
           for (int jj2 = 0; jj2 < IC; ++jj2) {
             if (jj2 < lo || jj2 > hi) continue;
             if constexpr (STIFF) G[jj2] = fma(b[jj2 * 2 + 1], x1, fma(b[jj2 * 2], x0, G[jj2]));
-            else G[jj2] = fma(b[jj2 * 2], x0, G[jj2]);
+            else G[jj2] = fma(b[jj2 * BJ], x0, G[jj2]);
           }
         }
       } else {
@@ -463,11 +470,11 @@ __device__ __forceinline__ void push_body(const PlanView& v, T* __restrict__ out
         for (int qq2 = 0; qq2 < qc2; ++qq2) {   // uniform trip count
           const T x0 = hb0[qq2 * J3];
           const T x1 = STIFF ? hb1[qq2 * J3] : T(0);
-          const T* b = B2 + __builtin_amdgcn_readfirstlane(qq2 * IC * 2);
+          const T* b = B2 + __builtin_amdgcn_readfirstlane(qq2 * BQ);
 #pragma unroll
           for (int jj2 = 0; jj2 < IC; ++jj2) {
             if constexpr (STIFF) G[jj2] = fma(b[jj2 * 2 + 1], x1, fma(b[jj2 * 2], x0, G[jj2]));
-            else G[jj2] = fma(b[jj2 * 2], x0, G[jj2]);
+            else G[jj2] = fma(b[jj2 * BJ], x0, G[jj2]);
           }
         }
       }

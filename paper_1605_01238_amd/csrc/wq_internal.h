@@ -82,6 +82,8 @@ struct DirView {
   float* op32;           // same in FP32
   double* bt64;          // [n][qcap][icap][2]  B^(alpha)_{is+jj}(x_{qs+qq})
   float* bt32;
+  double* b0t64;         // [n][qcap][icap]     B^(0) alone (the mass's operator, contiguous per qq)
+  float* b0t32;
   double* wt64;          // [n][qcap][4]        w^(o)_qq
   float* wt32;
   int64_t* prefix;       // n + 1  prefix sums of #I_i
@@ -129,7 +131,7 @@ struct BatchClassView {
 };
 
 struct Layout {
-  size_t knots[3], x[3], qspan[3], bv[3], bd[3], bw[3], w[3], op64[3], op32[3], bt64[3], bt32[3], wt64[3], wt32[3], prefix[3], colt64[3], colt32[3];
+  size_t knots[3], x[3], qspan[3], bv[3], bd[3], bw[3], w[3], op64[3], op32[3], bt64[3], bt32[3], b0t64[3], b0t32[3], wt64[3], wt32[3], prefix[3], colt64[3], colt32[3];
   size_t field, ybuf, ymass, ctrl, dctrl, wts, flags, total;
 };
 

@@ -69,6 +69,8 @@ void compute_layout(wq_plan* pl) {
     L.op32[k] = take(4 * n * ic * qc * 4);
     L.bt64[k] = take(2 * n * ic * qc * 8);
     L.bt32[k] = take(2 * n * ic * qc * 4);
+    L.b0t64[k] = take(n * ic * qc * 8);
+    L.b0t32[k] = take(n * ic * qc * 4);
     L.wt64[k] = take(4 * n * qc * 8);
     L.wt32[k] = take(4 * n * qc * 4);
     L.prefix[k] = take((n + 1) * 8);
@@ -127,6 +129,8 @@ wq::PlanView wq_plan::view() const {
     d.op32 = reinterpret_cast<float*>(ws + lay.op32[k]);
     d.bt64 = reinterpret_cast<double*>(ws + lay.bt64[k]);
     d.bt32 = reinterpret_cast<float*>(ws + lay.bt32[k]);
+    d.b0t64 = reinterpret_cast<double*>(ws + lay.b0t64[k]);
+    d.b0t32 = reinterpret_cast<float*>(ws + lay.b0t32[k]);
     d.wt64 = reinterpret_cast<double*>(ws + lay.wt64[k]);
     d.wt32 = reinterpret_cast<float*>(ws + lay.wt32[k]);
     d.prefix = reinterpret_cast<int64_t*>(ws + lay.prefix[k]);
@@ -271,11 +275,13 @@ wq_status wq_bind(wq_plan* plan, void* workspace, size_t bytes, hipStream_t stre
     if (e == hipSuccess) e = hipMemsetAsync(w + L.op32[k], 0, size_t(4) * ic * qc * 4, stream);
     if (e == hipSuccess) e = hipMemsetAsync(w + L.bt64[k], 0, size_t(2) * ic * qc * 8, stream);
     if (e == hipSuccess) e = hipMemsetAsync(w + L.bt32[k], 0, size_t(2) * ic * qc * 4, stream);
+    if (e == hipSuccess) e = hipMemsetAsync(w + L.b0t64[k], 0, size_t(ic) * qc * 8, stream);
+    if (e == hipSuccess) e = hipMemsetAsync(w + L.b0t32[k], 0, size_t(ic) * qc * 4, stream);
     if (e == hipSuccess) e = hipMemsetAsync(w + L.wt64[k], 0, size_t(4) * qc * 8, stream);
     if (e == hipSuccess) e = hipMemsetAsync(w + L.wt32[k], 0, size_t(4) * qc * 4, stream);
-    for (size_t off : {L.op64[k], L.bt64[k], L.wt64[k]})
+    for (size_t off : {L.op64[k], L.bt64[k], L.b0t64[k], L.wt64[k]})
       if (e == hipSuccess) e = hipMemcpyAsync(w + off, &one64, 8, hipMemcpyHostToDevice, stream);
-    for (size_t off : {L.op32[k], L.bt32[k], L.wt32[k]})
+    for (size_t off : {L.op32[k], L.bt32[k], L.b0t32[k], L.wt32[k]})
       if (e == hipSuccess) e = hipMemcpyAsync(w + off, &one32, 4, hipMemcpyHostToDevice, stream);
     if (e != hipSuccess) return hip_fail(plan, e, "wq_bind: trivial direction");
   }

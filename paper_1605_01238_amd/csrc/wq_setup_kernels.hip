@@ -479,6 +479,10 @@ __global__ __launch_bounds__(256) void k_rules(PlanView v) {
       if (pair < 2) {   // the B^(alpha) tables, alpha = pair
         d.bt64[(pq * IC + jj) * 2 + pair] = b;
         d.bt32[(pq * IC + jj) * 2 + pair] = float(b);
+        if (pair == 0) {
+          d.b0t64[pq * IC + jj] = b;
+          d.b0t32[pq * IC + jj] = float(b);
+        }
       }
     }
   }
