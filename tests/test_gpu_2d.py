@@ -94,6 +94,34 @@ def test_2d_large_sampled_rows():
         assert row_err <= FP64_TOL
 
 
+@pytest.mark.parametrize("name", ["p4_512el_plane", "p6_256el_plane"])
+def test_2d_bench_workloads_sampled_rows(name):
+    """The plane workloads of the benchmark, at their full size and with the
+    launch the benchmark times: sampled rows (corners, both boundary layers,
+    uniform rows; strips and runs of rows split at many places) against the
+    oracle, every matrix the workload forms, FP64 within 1e-12."""
+    import time
+    from oracle.assembly import Problem
+    from workloads import WORKLOADS, sample_rows
+    w = WORKLOADS[name]
+    kn, p, ctrl, cf = w.knots(), w.p, w.ctrl(), w.coefficient()
+    which = (1 if "mass" in w.which else 0) | (2 if "stiff" in w.which else 0)
+    plan, row_ptr, col_idx, mass, stiff = gpu_pipeline(kn, p, ctrl, cf, which=which)
+    print(f"[2d {name}] GPU done; oracle rules ...", flush=True)
+    t0 = time.time()
+    P = Problem(kn, p, ctrl, coef=cf)
+    n1, n2 = P.n
+    rows = sample_rows((n1, n2, 1), p, 40, 24, seed=9)
+    print(f"[2d {name}] oracle set up in {time.time() - t0:.0f} s; {len(rows)} rows", flush=True)
+    for wname, vals in (("mass", mass), ("stiff", stiff)):
+        if wname not in w.which:
+            continue
+        rp, v = gather_rows(row_ptr, vals, rows)
+        row_err, _, worst = compare_rows(P, rows, rp, v, wname)
+        print(f"[2d {name}] {wname}: row-normwise {row_err:.2e} (row {worst})", flush=True)
+        assert row_err <= FP64_TOL
+
+
 def test_2d_setup_twice_then_again():
     """setup(A) assemble, setup(B) assemble, setup(A) assemble on one plane
     plan, no synchronization in between: each result equals a fresh plan's."""
