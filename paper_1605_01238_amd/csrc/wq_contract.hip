@@ -584,16 +584,24 @@ struct PlaneShape {
   static constexpr int NB = STIFF ? 2 : 1;                // operators B2^(a) used
   static constexpr int C = STIFF ? WQ_PLANE_CS : WQ_PLANE_CM;
   static constexpr int UB = 64 / (C * NA);                // strip rows per pass of phase AB
-  static constexpr int CP = C + 1;                        // odd column strides: fewer bank conflicts
+  static constexpr int CP = C + 1;                        // odd column stride of the tile: fewer bank conflicts
   static constexpr int NCHT = STIFF ? 3 : 1;              // field channels in the tile
   // q2 points of a strip: spans max(0, i2a-p) .. min(n_el-1, i2a+K-1), at
   // most 2 per interior span and p+1 in a boundary one
   static constexpr int WMAX = 2 * K + 4 * P - 1;
-  static constexpr size_t GBUF = size_t(NG) * K * IC * CP;
+  // the mass keeps a compact copy of its operator: at each point only the
+  // p+1 functions that can be nonzero there (less LDS, more workgroups per
+  // compute unit); for the stiffness, whose two operators are read in the
+  // same loops, the full rows measured faster
+  static constexpr bool COMPACT = !STIFF;
+  static constexpr int PW = P + 1;                        // functions nonzero at a point
+  static constexpr int PWS = (PW + 1) & ~1;               // their even row stride in the compact copy
+  static constexpr size_t GBUF = size_t(NG) * C * K * IC;   // [g][c][u][jj2]: phase-C reads contiguous
   static constexpr size_t STAGE = size_t(K) * IC * IC;
   static constexpr size_t TILE = size_t(NCHT) * WMAX * CP;
   static constexpr size_t TSBUF = TILE > STAGE ? TILE : STAGE;   // the row stage shares the tile
-  static constexpr size_t BS = size_t(K) * NB * QC * ICP;
+  static constexpr size_t BS = COMPACT ? size_t(K) * NB * QC * PWS : size_t(K) * NB * QC * ICP;
+  static constexpr size_t BLO = COMPACT ? size_t(K) * QC : 1;   // first function of the window (int)
   static constexpr size_t WS = size_t(K) * QC * 4;
   static constexpr int NCT = 6 * (P + 1);                 // column-table entries
   static constexpr size_t CTAB = WQ_PLANE_CTAB ? size_t(C) * NCT : 1;
@@ -603,7 +611,7 @@ struct PlaneShape {
   // phase C instead of during it, and rows are stored one strip row at a
   // time), which buys a wave per SIMD where the count crosses 128 or 256
   static constexpr bool LEAN = sizeof(T) == 8 && P >= 4;
-  static constexpr size_t LDS_BYTES = (GBUF + TSBUF + BS + WS + CTAB) * sizeof(T);
+  static constexpr size_t LDS_BYTES = (GBUF + TSBUF + BS + WS + CTAB) * sizeof(T) + BLO * sizeof(int);
   static_assert(C * NA * UB <= 64 && C * NA * 2 * UB > 64, "phase AB fills most of the wave");
   static_assert(LDS_BYTES <= 64 * 1024, "LDS budget per workgroup");
 };
@@ -613,7 +621,8 @@ __device__ __forceinline__ void plane_body(const PlanView& v, T* __restrict__ ou
   using S = PlaneShape<P, T, STIFF>;
   constexpr int IC = S::IC, QC = S::QC, ICP = S::ICP, K = S::K, C = S::C, CP = S::CP, UB = S::UB;
   constexpr int NB = S::NB, NCHT = S::NCHT, WMAX = S::WMAX, TPL = S::TPL, CPL = S::CPL, NCT = S::NCT;
-  constexpr int GSTR = K * IC * CP;   // distance between groups in the G buffer
+  constexpr int PW = S::PW, PWS = S::PWS;
+  constexpr int GSTR = C * K * IC;   // distance between groups in the G buffer
   const DirView d1 = v.dir[0], d2 = v.dir[1];
   const int n1 = d1.n, n2 = d2.n, nq1 = d1.nq, nel1 = d1.nel;
   const int tid = threadIdx.x;
@@ -633,13 +642,14 @@ __device__ __forceinline__ void plane_body(const PlanView& v, T* __restrict__ ou
   q_range(i2a + nu - 1, P, d2.nel, wql, wqlc);
   const int nw = wql + wqlc - wq0;
 
-  __shared__ __align__(16) T gbuf[S::GBUF];     // [g][u][jj2][c] (column stride CP)
+  __shared__ __align__(16) T gbuf[S::GBUF];     // the groups G of a chunk, [g][c][u][jj2]
   // the field tile, [channel][q2 - wq0][c] (stride CP), is read in phase AB
   // only; in phase C it is free and holds the row stage [u][jj2][jj1]
   __shared__ __align__(16) T tsbuf[S::TSBUF];
   T* const tile = tsbuf;
   T* const stage = tsbuf;
-  __shared__ __align__(16) T bs[S::BS];         // [u][a][qq2][jj2] (stride ICP)
+  __shared__ __align__(16) T bs[S::BS];         // [u][a][qq2][r], jj2 = blo + r (compact), or [u][a][qq2][jj2] (stride ICP)
+  __shared__ int blo[S::BLO];                   // [u][qq2]: first function of the window, relative to I_i2
   __shared__ __align__(16) T wsh[S::WS];        // [u][qq2][o]
   __shared__ __align__(16) T ctab[S::CTAB];     // column tables of the chunk, [c][NCT]
   const T* __restrict__ fld = static_cast<const T*>(v.field);
@@ -651,9 +661,27 @@ __device__ __forceinline__ void plane_body(const PlanView& v, T* __restrict__ ou
   // the strip's dir-2 operators (B2^(a) rows, a-major) and weights
   {
     const T* __restrict__ bsrc = bt_t<T>(d2) + size_t(i2a) * QC * IC * 2;   // [u][qq2][jj2][a]
-    for (int t = tid; t < nu * QC * IC * 2; t += 64) {
-      const int a = t % 2, jj2 = (t / 2) % IC, qq2 = (t / (2 * IC)) % QC, u = t / (2 * IC * QC);
-      if (a < NB) bs[((u * NB + a) * QC + qq2) * ICP + jj2] = bsrc[t];
+    if constexpr (S::COMPACT) {
+      // at point q the functions qspan(q) .. qspan(q) + p can be nonzero; all
+      // of them lie in I_i2 when x_q lies in the support of B_i2
+      for (int t = tid; t < nu * QC; t += 64) {
+        const int u = t / QC, qq2 = t % QC;
+        int qs2, qc2, is2, ic2;
+        q_range(i2a + u, P, d2.nel, qs2, qc2);
+        i_range(i2a + u, P, n2, is2, ic2);
+        blo[t] = qq2 < qc2 ? d2.qspan[qs2 + qq2] - is2 : 0;
+      }
+      __syncthreads();
+      for (int t = tid; t < nu * NB * QC * PWS; t += 64) {
+        const int r = t % PWS, qq2 = (t / PWS) % QC, a = (t / (PWS * QC)) % NB, u = t / (PWS * QC * NB);
+        const int jj2 = blo[u * QC + qq2] + r;
+        bs[t] = r < PW && jj2 >= 0 && jj2 < IC ? bsrc[((u * QC + qq2) * IC + jj2) * 2 + a] : T(0);
+      }
+    } else {
+      for (int t = tid; t < nu * QC * IC * 2; t += 64) {
+        const int a = t % 2, jj2 = (t / 2) % IC, qq2 = (t / (2 * IC)) % QC, u = t / (2 * IC * QC);
+        if (a < NB) bs[((u * NB + a) * QC + qq2) * ICP + jj2] = bsrc[t];
+      }
     }
     const T* __restrict__ wsrc = wt_t<T>(d2) + size_t(i2a) * QC * 4;
     for (int t = tid; t < nu * QC * 4; t += 64) wsh[t] = wsrc[t];
@@ -779,29 +807,43 @@ __device__ __forceinline__ void plane_body(const PlanView& v, T* __restrict__ ou
           constexpr int RL0 = STIFF ? (A ? R11 : R01) : R00, RL1 = STIFF ? (A ? R10 : R00) : R00;
           const T* tr = tile + ((ah ? TC1 : TC0) * WMAX + (qs2 - wq0)) * CP + ac;   // + qq2 * CP
           const T* wr = wsh + u * QC * 4 + (ah ? RL1 : RL0);                        // + qq2 * 4
-          const T* br = bs + (u * NB + AI) * QC * ICP;                               // + qq2 * ICP + jj2
+          constexpr int BQ = S::COMPACT ? PWS : ICP;                                // operator copy: stride of qq2
+          const T* br = bs + (u * NB + AI) * QC * BQ;
           T G[IC];
 #pragma unroll
           for (int jj2 = 0; jj2 < IC; ++jj2) G[jj2] = T(0);
           if (band2) {
+            // interior row: the window of point qq2 starts at (qq2 + 1) / 2
 #pragma unroll
             for (int qq2 = 0; qq2 < 2 * P + 1; ++qq2) {
               const T x = wr[qq2 * 4] * tr[qq2 * CP];
               const int lo = (qq2 + 1) / 2, hi = qq2 / 2 + P;
 #pragma unroll
               for (int jj2 = 0; jj2 < IC; ++jj2)
-                if (jj2 >= lo && jj2 <= hi) G[jj2] = fma(br[qq2 * ICP + jj2], x, G[jj2]);
+                if (jj2 >= lo && jj2 <= hi)
+                  G[jj2] = fma(br[qq2 * BQ + (S::COMPACT ? jj2 - lo : jj2)], x, G[jj2]);
             }
           } else {
             for (int qq2 = 0; qq2 < qc2; ++qq2) {
               const T x = wr[qq2 * 4] * tr[qq2 * CP];
+              const T* bq = br + qq2 * BQ;
+              if constexpr (S::COMPACT) {
+                const int lo = blo[u * QC + qq2];
 #pragma unroll
-              for (int jj2 = 0; jj2 < IC; ++jj2) G[jj2] = fma(br[qq2 * ICP + jj2], x, G[jj2]);
+                for (int jj2 = 0; jj2 < IC; ++jj2) {
+                  const int r = jj2 - lo;
+                  const T bv = bq[r < 0 ? 0 : (r > P ? P : r)];
+                  G[jj2] = fma(r >= 0 && r <= P ? bv : T(0), x, G[jj2]);
+                }
+              } else {
+#pragma unroll
+                for (int jj2 = 0; jj2 < IC; ++jj2) G[jj2] = fma(bq[jj2], x, G[jj2]);
+              }
             }
           }
-          T* gb = gbuf + ((ah ? G1 : G0) * K + u) * IC * CP + ac;
+          T* gb = gbuf + (((ah ? G1 : G0) * C + ac) * K + u) * IC;
 #pragma unroll
-          for (int jj2 = 0; jj2 < IC; ++jj2) gb[jj2 * CP] = G[jj2];
+          for (int jj2 = 0; jj2 < IC; ++jj2) gb[jj2] = G[jj2];
         };
         if constexpr (STIFF) {
           group(std::integral_constant<int, 1>{});
@@ -825,7 +867,7 @@ __device__ __forceinline__ void plane_body(const PlanView& v, T* __restrict__ ou
       }
       if (cl) {
         const T* ct = WQ_PLANE_CTAB ? ctab + c * NCT : CT + int64_t(__builtin_amdgcn_readfirstlane(q1c)) * NCT;
-        const T* gb = gbuf + tid * CP + c;   // (g, u, jj2) = (g, cu, cj2)
+        const T* gb = gbuf + c * K * IC + tid;   // (g, c, u, jj2) = (g, c, cu, cj2)
         if constexpr (STIFF) {
           const T g00 = gb[0], g10 = gb[GSTR], g01 = gb[2 * GSTR], g11 = gb[3 * GSTR];
 #pragma unroll
