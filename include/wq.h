@@ -270,7 +270,9 @@ wq_status wq_assemble_request(wq_plan* plan, void* ctx, size_t ctx_bytes, const 
  * their own (created, bound and set up as usual; distinct plans; any mix of
  * degree, size, d and precision).  Per class of equal (p, d, precision) one
  * launch forms the first contraction of all its patches and one persistent
- * launch forms all their rows from a device work queue.  Values equal
+ * launch forms all their rows from a device work queue, or (a schedule the
+ * autotuner may pick) the single-patch kernels run patch after patch on
+ * the class's stream.  Classes run concurrently.  Values equal
  * wq_assemble's bit for bit.
  *   wq_batch_create  host only; n plans, copied as pointers (the plans must
  *                    outlive the batch and keep their workspaces while the
@@ -286,7 +288,8 @@ wq_status wq_assemble_request(wq_plan* plan, void* ctx, size_t ctx_bytes, const 
  *                    again.
  *   wq_batch_tune    autotuner: per class, times the candidate schedules
  *                    (runs of rows per pencil, persistent workgroups per
- *                    compute unit) on the bound patches and keeps the fastest
+ *                    compute unit; or one launch per patch) on the bound
+ *                    patches and keeps the fastest
  *                    for `which`; synchronizes stream.  Requires wq_setup of
  *                    every plan; overwrites the outputs.
  *   wq_batch_assemble  forms `which` for every patch, asynchronously on
@@ -295,7 +298,8 @@ wq_status wq_assemble_request(wq_plan* plan, void* ctx, size_t ctx_bytes, const 
  *                    after bind or tune) and replayed; needs a stream other
  *                    than the legacy default stream.
  *   wq_batch_schedule  class k: info[6] = {p, d, precision, patches,
- *                    work-item target, workgroups per compute unit}.
+ *                    work-item target, workgroups per compute unit (0: one
+ *                    launch per patch)}.
  * Errors: WQ_EINVAL, WQ_ENOSPACE, WQ_ESTATE (unbound batch or plan, plan not
  * set up), WQ_EDEVICE; wq_batch_last_error gives the message.  Like plans, a
  * batch is a host object, not thread-safe; a batch and the plans it holds

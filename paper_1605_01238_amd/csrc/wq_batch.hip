@@ -15,6 +15,7 @@
 #include <cstring>
 #include <new>
 #include <string>
+#include <utility>
 #include <vector>
 
 #include "wq_internal.h"
@@ -151,11 +152,20 @@ hipError_t upload(wq_batch* b, hipStream_t s) {
   return hipMemcpyAsync(b->ws, b->img.data(), b->total_bytes, hipMemcpyHostToDevice, s);
 }
 
-// The launches of class k (both matrices) on stream s.
+// The launches of class k (both matrices) on stream s: the class's two
+// launches over its device work queues, or (schedule wgs_per_cu = 0) the
+// single-patch kernels patch after patch.
 hipError_t enqueue_class(wq_batch* b, size_t k, int which, hipStream_t s) {
   const wq_batch::Class& c = b->classes[k];
-  const wq::BatchClassView v = b->view(c);
   hipError_t e = hipSuccess;
+  if (c.wgs_per_cu == 0) {
+    for (size_t m = 0; m < c.members.size() && e == hipSuccess; ++m) {
+      const int idx = c.members[m];
+      e = wq::launch_assemble(b->plans[idx]->view(), which, b->mass[idx], b->stiff[idx], s);
+    }
+    return e;
+  }
+  const wq::BatchClassView v = b->view(c);
   for (int stiff = 0; stiff < 2 && e == hipSuccess; ++stiff) {
     if (!(which & (stiff ? WQ_STIFF : WQ_MASS)) || c.total[stiff] == 0) continue;
     const int grid = std::max(1, std::min(c.total[stiff], c.wgs_per_cu * b->n_cu));
@@ -319,26 +329,31 @@ wq_status wq_batch_tune(wq_batch* b, int which, hipStream_t stream) {
     wq_batch::Class& c = b->classes[k];
     float best = 1e30f;
     int best_t = c.seg_target, best_g = c.wgs_per_cu;
+    // the persistent schedules, then one launch per patch (g = 0)
+    std::vector<std::pair<int, int>> cands;
     for (int tgt : kSegTargets)
-      for (int g : kWgsPerCu) {
-        c.seg_target = tgt;
-        c.wgs_per_cu = g;
-        fill_schedule(b, c);
-        e = upload(b, stream);
-        if (e == hipSuccess) e = enqueue(b, which, stream, int(k));   // warm-up
-        if (e == hipSuccess) e = hipEventRecord(t0, stream);
-        for (int rep = 0; rep < 2 && e == hipSuccess; ++rep) e = enqueue(b, which, stream, int(k));
-        if (e == hipSuccess) e = hipEventRecord(t1, stream);
-        if (e == hipSuccess) e = hipEventSynchronize(t1);
-        float ms = 0.f;
-        if (e == hipSuccess) e = hipEventElapsedTime(&ms, t0, t1);
-        if (e != hipSuccess) break;
-        if (ms < best) {
-          best = ms;
-          best_t = tgt;
-          best_g = g;
-        }
+      for (int g : kWgsPerCu) cands.emplace_back(tgt, g);
+    cands.emplace_back(0, 0);
+    for (const auto& cand : cands) {
+      const int tgt = cand.first, g = cand.second;
+      c.seg_target = tgt;
+      c.wgs_per_cu = g;
+      fill_schedule(b, c);
+      e = upload(b, stream);
+      if (e == hipSuccess) e = enqueue(b, which, stream, int(k));   // warm-up
+      if (e == hipSuccess) e = hipEventRecord(t0, stream);
+      for (int rep = 0; rep < 2 && e == hipSuccess; ++rep) e = enqueue(b, which, stream, int(k));
+      if (e == hipSuccess) e = hipEventRecord(t1, stream);
+      if (e == hipSuccess) e = hipEventSynchronize(t1);
+      float ms = 0.f;
+      if (e == hipSuccess) e = hipEventElapsedTime(&ms, t0, t1);
+      if (e != hipSuccess) break;
+      if (ms < best) {
+        best = ms;
+        best_t = tgt;
+        best_g = g;
       }
+    }
     c.seg_target = best_t;
     c.wgs_per_cu = best_g;
     fill_schedule(b, c);
