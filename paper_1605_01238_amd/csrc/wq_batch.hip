@@ -69,14 +69,14 @@ struct wq_batch {
     if (ev_fork) (void)hipEventDestroy(ev_fork);
   }
   hipError_t make_side() {
-    const size_t ns = std::min<size_t>(kSideStreams, classes.size());
+    const size_t ns = std::min<size_t>(kSideStreams, 2 * classes.size());
     hipError_t e = hipSuccess;
     while (e == hipSuccess && side.size() < ns) {
       hipStream_t s = nullptr;
       e = hipStreamCreateWithFlags(&s, hipStreamNonBlocking);
       if (e == hipSuccess) side.push_back(s);
     }
-    while (e == hipSuccess && ev_done.size() < classes.size()) {
+    while (e == hipSuccess && ev_done.size() < 2 * classes.size()) {
       hipEvent_t ev = nullptr;
       e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
       if (e == hipSuccess) ev_done.push_back(ev);
@@ -155,13 +155,18 @@ hipError_t upload(wq_batch* b, hipStream_t s) {
 // The launches of class k (both matrices) on stream s: the class's two
 // launches over its device work queues, or (schedule wgs_per_cu = 0) the
 // single-patch kernels patch after patch.
-hipError_t enqueue_class(wq_batch* b, size_t k, int which, hipStream_t s) {
+// mass_own_y: the mass uses each plan's own mass buffer for the first
+// contraction, so that it may run beside the stiffness of the same plans.
+hipError_t enqueue_class(wq_batch* b, size_t k, int which, hipStream_t s, bool mass_own_y = false) {
   const wq_batch::Class& c = b->classes[k];
   hipError_t e = hipSuccess;
   if (c.wgs_per_cu == 0) {
     for (size_t m = 0; m < c.members.size() && e == hipSuccess; ++m) {
       const int idx = c.members[m];
-      e = wq::launch_assemble(b->plans[idx]->view(), which, b->mass[idx], b->stiff[idx], s);
+      const wq_plan* pl = b->plans[idx];
+      wq::PlanView v = pl->view();
+      if (mass_own_y) v.ybuf = pl->ws + pl->lay.ymass;
+      e = wq::launch_assemble(v, which, b->mass[idx], b->stiff[idx], s);
     }
     return e;
   }
@@ -188,12 +193,20 @@ hipError_t enqueue(wq_batch* b, int which, hipStream_t s, int only_class = -1) {
   if (e == hipSuccess && b->side.empty()) e = hipErrorInvalidHandle;   // made by wq_batch_bind
   if (e == hipSuccess) e = hipEventRecord(b->ev_fork, s);
   for (size_t j = 0; j < b->side.size() && e == hipSuccess; ++j) e = hipStreamWaitEvent(b->side[j], b->ev_fork, 0);
+  // units of work dealt round-robin to the side streams: a class, or, for
+  // a class launched patch after patch with both matrices, its masses and
+  // its stiffnesses as two units (the masses on their own buffers)
+  size_t u = 0;
   for (size_t k = 0; k < b->classes.size() && e == hipSuccess; ++k) {
-    hipStream_t sk = b->side[k % b->side.size()];
-    e = enqueue_class(b, k, which, sk);
-    if (e == hipSuccess) e = hipEventRecord(b->ev_done[k], sk);
+    const bool split = b->classes[k].wgs_per_cu == 0 && which == (WQ_MASS | WQ_STIFF);
+    for (int part = 0; part < (split ? 2 : 1) && e == hipSuccess; ++part, ++u) {
+      hipStream_t su = b->side[u % b->side.size()];
+      const int w = split ? (part == 0 ? WQ_MASS : WQ_STIFF) : which;
+      e = enqueue_class(b, k, w, su, split && part == 0);
+      if (e == hipSuccess) e = hipEventRecord(b->ev_done[u], su);
+    }
   }
-  for (size_t k = 0; k < b->classes.size() && e == hipSuccess; ++k) e = hipStreamWaitEvent(s, b->ev_done[k], 0);
+  for (size_t j = 0; j < u && e == hipSuccess; ++j) e = hipStreamWaitEvent(s, b->ev_done[j], 0);
   return e;
 }
 
