@@ -224,6 +224,9 @@ class Batch:
         _bcheck(_wq.wq_batch_assemble(self._h, which, int(use_graph), _stream(stream)), self._h)
 
     def schedule(self):
+        """Per class: degree, dimension, precision, patch count and the
+        schedule (work-item target and persistent workgroups per compute unit;
+        wgs_per_cu 0: the single-patch kernels, patch after patch)."""
         out = []
         info = (C.c_int * 6)()
         for k in range(self.n_classes):
