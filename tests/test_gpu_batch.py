@@ -88,6 +88,21 @@ def test_batch_graph_replays():
         torch.cuda.synchronize()
         _equal_all(refs, outs)
         print(f"[batch graph] replay {rep} equal ({float(junk):.1f})", flush=True)
+    # after tuning (schedules may now launch the single-patch kernels patch
+    # after patch, masses and stiffnesses on separate side streams) the
+    # graph is captured again; its replays must still be exact
+    b.tune(3)
+    print(f"[batch graph] tuned: {b.schedule()}", flush=True)
+    for rep in range(2):
+        for o in outs:
+            o[0].fill_(float("nan"))
+            o[1].fill_(float("nan"))
+        torch.cuda.synchronize()
+        with torch.cuda.stream(side):
+            b.assemble(3, use_graph=True, stream=side)
+        side.synchronize()
+        _equal_all(refs, outs)
+        print(f"[batch graph] tuned replay {rep} equal", flush=True)
 
 
 def test_batch_sampled_rows_against_oracle():
